@@ -1,0 +1,73 @@
+"""Named synthetic workloads: sizes and parameters only (no method arithmetic).
+
+Each entry mirrors one evaluation setting of the SINDI search path on
+SPLADE-shaped synthetic data: the paper's SPLADE-FULL corpus (8,841,823
+documents, ~127 non-zeros each, vocabulary ~30K; Sec. 5.1, Table "datasets")
+stands behind the 8.8M-document setting, and the BGE-M3-shaped AntSparse
+vocabulary (250K) behind the differentiation setting.  Real datasets are not
+used; every corpus here is drawn by :mod:`synth` from its seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import synth
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n_docs: int
+    vocab: int
+    doc_nnz: tuple
+    n_queries: int
+    query_nnz: tuple
+    alpha: float  # document mass-ratio pruning (1.0 = none)
+    window: int  # window size lambda, documents
+    gamma: int  # rerank pool
+    k: int
+    beta: float = 1.0  # query mass-ratio pruning (1.0 = none)
+    value_dtype: str = "f32"  # posting value storage: f32 / f16 / bf16
+    seed: int = 0
+    terms: tuple = ("zipf", 1.1)
+    values: tuple = ("lognormal", 0.0, 0.8)
+    clip: tuple = (1, 512)
+    extra: dict = field(default_factory=dict)
+
+    def scaled(self, n_docs: int, n_queries: int | None = None) -> "Workload":
+        return replace(self, n_docs=n_docs,
+                       n_queries=self.n_queries if n_queries is None else n_queries,
+                       name=f"{self.name}@{n_docs}")
+
+    def corpus(self) -> synth.Csr:
+        return synth.generate(self.n_docs, self.vocab, nnz=self.doc_nnz, clip=self.clip,
+                              terms=self.terms, values=self.values, seed=self.seed,
+                              stream=synth.STREAM_DOCS)
+
+    def queries(self, n: int | None = None, row0: int = 0) -> synth.Csr:
+        return synth.generate(self.n_queries if n is None else n, self.vocab,
+                              nnz=self.query_nnz, clip=self.clip, terms=self.terms,
+                              values=self.values, seed=self.seed,
+                              stream=synth.STREAM_QUERIES, row0=row0)
+
+
+WORKLOADS = {
+    # Plain method, exact: no pruning, one window, top-10.
+    "tiny": Workload("tiny", 10_000, 30_522, ("poisson", 120.0), 100, ("poisson", 30.0),
+                     alpha=1.0, window=10_000, gamma=10, k=10),
+    # Mass-ratio pruned index, FP32 values, rerank pool 500, top-50.
+    "pruned-1m": Workload("pruned-1m", 1_000_000, 30_522, ("poisson", 120.0), 1_000,
+                          ("poisson", 30.0), alpha=0.5, window=100_000, gamma=500, k=50),
+    # SPLADE-FULL-sized corpus, half-precision posting values, FP32 rerank.
+    "splade-8.8m": Workload("splade-8.8m", 8_800_000, 30_522, ("poisson", 125.0), 7_000,
+                            ("poisson", 35.0), alpha=0.5, window=100_000, gamma=500, k=50,
+                            value_dtype="f16"),
+    # Serving: same index, queries of uniform length 5..200, k in {10, 50, 100}.
+    "serving": Workload("serving", 8_800_000, 30_522, ("poisson", 125.0), 20_000,
+                        ("uniform", 5, 200), alpha=0.5, window=100_000, gamma=500, k=100,
+                        value_dtype="f16", extra={"rates": (2e3, 5e3, 1e4, 2e4, 5e4)}),
+    # Differentiation: multilingual-sized vocabulary, exact top-100 candidates.
+    "diff-1m": Workload("diff-1m", 1_000_000, 250_002, ("poisson", 180.0), 256,
+                        ("poisson", 40.0), alpha=1.0, window=100_000, gamma=100, k=100,
+                        extra={"tau": 20.0}),
+}
