@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput of the SINDI search path on one MI355X.
+
+One step = one ``sindi_search`` over the whole query set of the workload
+(coarse accumulate over the mass-ratio-pruned window lists, per-query
+candidate threshold, top-gamma, exact FP32 rerank, top-k), with the index
+and the queries already resident in HBM.  Prints one JSON line.
+
+Default workload: 8.8M synthetic SPLADE-shaped documents (vocabulary 30,522,
+~125 non-zeros each), 7,000 queries (~35 non-zeros), alpha = 0.5,
+lambda = 100,000, gamma = 500, k = 50, FP16 posting values.  The real
+MS MARCO / SPLADE data is not used; the generator draws the same shapes.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batch_union_postings(qc, term_len, batch):
+    """Sum over batches of B consecutive queries of sum_{j in union} |I'_j|."""
+    tot = 0
+    n = qc.n_rows
+    for b0 in range(0, n, batch):
+        a, b = int(qc.indptr[b0]), int(qc.indptr[min(n, b0 + batch)])
+        u = np.unique(qc.indices[a:b])
+        tot += int(term_len[u].sum())
+    return tot
+
+
+def per_query_postings(qc, term_len):
+    return int(term_len[qc.indices].sum())
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="splade-8.8m")
+    ap.add_argument("--value-dtype", default=None, help="posting value storage f32/f16/bf16")
+    ap.add_argument("--n-docs", type=int, default=0, help="override corpus size (development)")
+    ap.add_argument("--queries", type=int, default=0, help="override query count")
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--alpha", type=float, default=None)
+    ap.add_argument("--gamma", type=int, default=0)
+    ap.add_argument("--recall-queries", type=int, default=128)
+    ap.add_argument("--oracle-queries", type=int, default=256)
+    ap.add_argument("--no-oracle", action="store_true", help="skip recall and the CPU baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index is not "
+              "sharded across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from synth.workloads import WORKLOADS
+    import paper_2509_08395_amd as sindi
+    from paper_2509_08395_amd import _lib
+
+    wl = WORKLOADS[args.workload]
+    if args.n_docs:
+        wl = wl.scaled(args.n_docs)
+    n_q = args.queries or wl.n_queries
+    dtype = args.value_dtype or wl.value_dtype
+    alpha = wl.alpha if args.alpha is None else args.alpha
+    gamma = args.gamma or wl.gamma
+    k = wl.k
+
+    t = time.time()
+    corpus = wl.corpus()
+    queries = wl.queries(n_q)
+    gen_s = time.time() - t
+    log(f"generated {corpus.n_rows} docs ({corpus.nnz} nnz), {queries.n_rows} queries in {gen_s:.1f}s")
+
+    torch.cuda.init()
+    t = time.time()
+    idx = sindi.Index(corpus, alpha=alpha, window=wl.window, value_dtype=dtype, tile=args.tile)
+    build_s = time.time() - t
+    info = idx.info()
+    log(f"built index in {build_s:.1f}s: {info}")
+    dq = sindi.DeviceCsr.from_host(queries)
+    ids = torch.empty((n_q, k), dtype=torch.int64, device="cuda")
+    scores = torch.empty((n_q, k), dtype=torch.float32, device="cuda")
+    kw = dict(gamma=gamma, batch=args.batch, out=(ids, scores))
+
+    for _ in range(args.warmup):
+        idx.search(dq, k, **kw)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    sindi.profile_enable(True)
+    sindi.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        idx.search(dq, k, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sindi.profile_read(reset=True)
+    sindi.profile_enable(False)
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    qps = n_q * args.steps / elapsed
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {qps:.0f} QPS; kernels {prof}")
+
+    # roofline of the dominant kernel (scoring accumulate): algorithmic bytes per launch
+    ex_off = idx.export()["term_off"]
+    term_len = np.diff(ex_off.astype(np.int64), axis=1).sum(axis=0)
+    del ex_off
+    vbytes = {"f32": 4, "f16": 2, "bf16": 2}[dtype]
+    bpp = 2 + vbytes
+    batch = args.batch or 4
+    union_post = batch_union_postings(queries, term_len, batch)
+    query_post = per_query_postings(queries, term_len)
+    offs_bytes = int(queries.nnz) * int(info["n_tiles"]) * 8
+    algo_bytes = union_post * bpp + offs_bytes
+    n_launch, acc_ms = prof["accumulate_score"]
+    acc_ms_avg = acc_ms / max(n_launch, 1)
+    achieved = algo_bytes / (acc_ms_avg * 1e-3) / 1e9 if acc_ms_avg > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_accumulate (scoring pass)", "launch_ms": round(acc_ms_avg, 3),
+                "bytes_per_launch": algo_bytes, "batch": batch,
+                "postings_per_launch_union": union_post,
+                "useful_postings_per_s": round(query_post / (acc_ms_avg * 1e-3), 1) if acc_ms_avg else 0}
+
+    result = {
+        "metric": "QPS at Recall@50>=99% vs exact oracle, 8.8M docs; % HBM roofline; p99 ms",
+        "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "n_docs": corpus.n_rows, "vocab": wl.vocab,
+                   "n_queries": n_q, "value_storage": dtype, "alpha": alpha,
+                   "window": wl.window, "gamma": gamma, "k": k, "beta": wl.beta,
+                   "batch": batch, "tile": info["tile_max"], "n_tiles": info["n_tiles"],
+                   "n_postings": info["n_postings"]},
+        "latency_ms_batch": round(ms_per_step, 3),
+        "kernels_ms_per_step": {n: round(v[1] / args.steps, 3) for n, v in prof.items()},
+        "build_s": round(build_s, 2),
+        "roofline": roofline,
+    }
+
+    if not args.no_oracle:
+        import oracle  # CPU baseline and recall only
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        gids = ids.cpu().numpy()
+        rsel = np.linspace(0, n_q - 1, min(args.recall_queries, n_q)).astype(np.int64)
+        qs = queries.take_rows(rsel)
+        t = time.time()
+        truth, _ = oracle.exact_topk(corpus, qs, k, threads=threads)
+        exact_s = time.time() - t
+        rec = oracle.recall_at_k(gids[rsel], truth)
+        log(f"recall@{k} on {len(rsel)} queries: {rec:.5f} (exact oracle {exact_s:.1f}s)")
+        osel = np.arange(min(args.oracle_queries, n_q))
+        qo = queries.take_rows(osel)
+        t = time.time()
+        keep = oracle.mass_prune(corpus, alpha, threads=threads)
+        oidx = oracle.build_index(corpus, wl.window, keep)
+        del keep
+        oracle_build_s = time.time() - t
+        t = time.time()
+        oracle.approx_search(oidx, corpus, qo, wl.beta, gamma, k, threads=threads)
+        oracle_s = time.time() - t
+        log(f"oracle Alg. 4 on {len(osel)} queries: {oracle_s:.1f}s (index {oracle_build_s:.1f}s)")
+        result["recall_at_k"] = round(rec, 5)
+        result["recall_sample"] = f"{len(rsel)} of {n_q} queries, evenly spaced; exact FP64 oracle"
+        result["cpu_baseline"] = {
+            "value": round(len(osel) / oracle_s, 3), "unit": "queries/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {len(osel)} of {n_q} queries, FP64 Alg. 4 (same alpha, gamma, k), "
+                      f"{oracle_s:.1f}s; exact FP64 top-{k}: {len(rsel) / exact_s:.3f} queries/s",
+            "cpu": _cpu_model()}
+        if rec < 0.99:
+            result["note"] = f"recall {rec:.4f} below 0.99"
+    print(json.dumps(result), flush=True)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * sindi.h -- C ABI of the MI355X (gfx950) SINDI sparse maximum-inner-product
+ * search library (arXiv 2509.08395: "SINDI", a value-storing, window-
+ * partitioned inverted index with mass-ratio pruning and exact reordering).
+ *
+ * Conventions for every entry point
+ *   - Return a sindi_status; SINDI_OK (0) on success.  On failure nothing is
+ *     written to the caller's output buffers and sindi_last_error() returns a
+ *     thread-local message.  No C++ exception crosses this interface.
+ *   - "stream" is a hipStream_t passed as void*; NULL is the default stream.
+ *     Every device operation of a call is enqueued on it.
+ *   - The caller owns every buffer it passes.  The library keeps no pointer to
+ *     them after the call returns.
+ *   - Ranking order: score descending, equal scores by ascending document id.
+ *   - Scores are inner products delta(x, q) (Def. 2), not the 1 - delta
+ *     distance the paper's Alg. 4 ranks by.
+ */
+#ifndef SINDI_H
+#define SINDI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SINDI_OK = 0,
+    SINDI_E_INVALID = -1,  /* malformed input or parameter                     */
+    SINDI_E_RANGE = -2,    /* a value does not fit the requested storage type   */
+    SINDI_E_OOM = -3,      /* device or host allocation failed                  */
+    SINDI_E_HIP = -4,      /* a HIP runtime call failed                         */
+    SINDI_E_INTERNAL = -6  /* a library invariant failed                        */
+} sindi_status;
+
+/* Storage type of posting values (document entries in the inverted lists). */
+typedef enum { SINDI_F32 = 0, SINDI_F16 = 1, SINDI_BF16 = 2 } sindi_dtype;
+
+/*
+ * A set of sparse vectors in CSR form (Def. 1: a vector is the set of its
+ * non-zero entries).  Row r owns entries [indptr[r], indptr[r+1]): term ids
+ * in indices[] (strictly ascending within a row, each in [0, n_cols)) and
+ * their values in values[] (finite float32).  Explicit zero values are
+ * allowed and are treated as absent entries.
+ * on_device = 0: the three arrays are host memory.
+ * on_device = 1: they are device memory of the current HIP device (only
+ *                sindi_search / sindi_search_coarse / the score calls accept
+ *                device-resident queries; sindi_build reads host memory).
+ */
+typedef struct {
+    int64_t n_rows;
+    int64_t n_cols;          /* vocabulary size d                            */
+    int64_t nnz;             /* == indptr[n_rows]                            */
+    const int64_t *indptr;   /* [n_rows + 1], indptr[0] == 0, non-decreasing */
+    const int32_t *indices;  /* [nnz]                                        */
+    const float *values;     /* [nnz]                                        */
+    int32_t on_device;
+    int32_t reserved_;
+} sindi_csr;
+
+/* Index build parameters (Alg. 3, ApproximateSindiConstruction). */
+typedef struct {
+    double alpha;            /* mass-ratio pruning ratio, (0, 1]; 1 = keep all (Def. 6) */
+    int64_t window;          /* window size lambda in documents, >= 1 (Sec. 3.3.1)       */
+    int32_t value_dtype;     /* sindi_dtype of the stored posting values                 */
+    int32_t tile;            /* max documents per on-chip score tile; 0 = library default;
+                                every window is split into equal tiles of at most this
+                                many documents; at most 65536                            */
+} sindi_build_params;
+
+/* Search parameters (Alg. 4, ApproximateSindiSearch).  Zero fields take defaults. */
+typedef struct {
+    double beta;             /* query mass-ratio pruning for the coarse stage, (0, 1]; 0 -> 1 */
+    int32_t gamma;           /* reorder pool size, k <= gamma <= 4096; 0 -> max(k, 500)      */
+    int32_t batch;           /* queries sharing one pass over a tile's lists: 1, 2, 4 or 8;
+                                0 -> library default                                        */
+    int32_t cand_cap;        /* per-query candidate buffer entries; 0 -> library default     */
+    int32_t sample_tiles;    /* tiles scored first to set each query's candidate threshold;
+                                0 -> library default, -1 -> no threshold (keep every doc)    */
+} sindi_search_params;
+
+/* Summary of a built index. */
+typedef struct {
+    int64_t n_docs, n_cols, nnz;   /* unpruned corpus                          */
+    int64_t n_postings;            /* entries kept by pruning = index postings */
+    int64_t window;                /* lambda                                   */
+    int64_t n_windows;             /* sigma = ceil(n_docs / window)            */
+    int64_t n_tiles;               /* score tiles (windows split into tiles)   */
+    int32_t tile_max;              /* largest tile, documents                  */
+    int32_t value_dtype;
+    double alpha;
+    int64_t device_bytes;          /* HBM held by the index                    */
+} sindi_index_info;
+
+typedef struct sindi_index sindi_index;
+
+/*
+ * Build the index of Alg. 3 from a host CSR corpus: every document is cut to
+ * its alpha-mass subvector (Defs. 5-6: entries ranked by |x| descending, ties
+ * by ascending term id; the shortest prefix whose |x| sum, accumulated in
+ * FP64 in that order, reaches alpha times the row's mass), and the kept
+ * entries are laid out as the value-storing inverted lists I_{j,w} of Alg. 1
+ * (document ids ascending inside every list), each window further split into
+ * score tiles.  The unpruned corpus is kept too, for the exact rerank of
+ * Alg. 4.  Both live in device memory owned by the returned handle.
+ * Values stored as FP16/BF16 are rounded to nearest even; an FP16 overflow
+ * (|x| > 65504) returns SINDI_E_RANGE.
+ * corpus->on_device must be 0.  *out receives the handle (free with
+ * sindi_index_free).  Synchronous: returns after the upload completes.
+ */
+sindi_status sindi_build(const sindi_csr *corpus, const sindi_build_params *params, void *stream,
+                         sindi_index **out);
+
+void sindi_index_free(sindi_index *idx);
+
+sindi_status sindi_index_get_info(const sindi_index *idx, sindi_index_info *out);
+
+/*
+ * Copy the device index to host buffers (for checking the layout).
+ *   tile_doc   int64 [n_tiles + 1]  first document of each tile
+ *   tile_post  int64 [n_tiles + 1]  first posting of each tile
+ *   term_off   uint32 [n_tiles * (n_cols + 1)]  list (term j, tile t) occupies
+ *              postings tile_post[t] + [term_off[t*(n_cols+1)+j], ...[j+1])
+ *   post_doc   uint16 [n_postings]  document id minus tile_doc[t]
+ *   post_val   [n_postings] values as stored (4 or 2 bytes each)
+ * Any pointer may be NULL to skip that array.
+ */
+sindi_status sindi_index_export(const sindi_index *idx, int64_t *tile_doc, int64_t *tile_post,
+                                uint32_t *term_off, uint16_t *post_doc, void *post_val);
+
+/*
+ * Alg. 4: for every query q, the coarse pool = the first gamma documents by
+ * the inner product of beta-mass(q) with the pruned documents (Alg. 2 over
+ * the index); each pooled document's exact delta(x, q) in FP32 from the
+ * unpruned vector and the full query; the first k by that score.
+ *   queries  CSR over the index's vocabulary (host or device memory)
+ *   out_ids  device int64 [n_rows * k]; -1 where fewer than k documents exist
+ *   out_scores device float [n_rows * k]; -inf for padding
+ * Blocks until the results are in out_ids / out_scores.
+ */
+sindi_status sindi_search(const sindi_index *idx, const sindi_csr *queries, int32_t k,
+                          const sindi_search_params *params, int64_t *out_ids, float *out_scores,
+                          void *stream);
+
+/*
+ * Alg. 2 (PreciseSindiSearch) over the index: the first k documents by the
+ * coarse score (inner product of beta-mass(q) with the pruned documents as
+ * stored, FP32 accumulation), no rerank.  Same buffers as sindi_search.
+ */
+sindi_status sindi_search_coarse(const sindi_index *idx, const sindi_csr *queries, int32_t k,
+                                 const sindi_search_params *params, int64_t *out_ids,
+                                 float *out_scores, void *stream);
+
+/*
+ * Scores of listed candidates: out_scores[b*n_cand + c] = delta(q_b, x_{cand})
+ * (Def. 2) in FP32 from the unpruned corpus; cand id -1 gives 0.
+ *   queries  CSR (device memory), cand_ids device int64 [n_rows * n_cand]
+ */
+sindi_status sindi_score_forward(const sindi_index *idx, const sindi_csr *queries,
+                                 const int64_t *cand_ids, int32_t n_cand, float *out_scores,
+                                 void *stream);
+
+/*
+ * Backward of sindi_score_forward.  The score is bilinear in the values, so
+ * with G = dL/dscore:
+ *   grad_query_values[e] += sum_c G[b,c] * x_c[t]     (entry e = (b, t))
+ *   grad_doc_values[e']  += sum_b G[b,c] * q_b[t]     (entry e' = (c, t))
+ * over common dimensions t only; entries outside every intersection are
+ * untouched.  grad_query_values is aligned with queries->values (device,
+ * [queries->nnz]); grad_doc_values with the corpus values given to
+ * sindi_build (device, [nnz]).  Either may be NULL.  Accumulates (+=).
+ * Candidate ids -1 are skipped.
+ */
+sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queries,
+                                  const int64_t *cand_ids, int32_t n_cand,
+                                  const float *grad_scores, float *grad_query_values,
+                                  float *grad_doc_values, void *stream);
+
+/*
+ * Kernel timing.  While enabled, the library records a pair of HIP events on
+ * the caller's stream around every kernel that sindi_search /
+ * sindi_search_coarse launch; sindi_profile_read waits for the recorded
+ * events and reports, per kernel class, the number of launches and the sum of
+ * their GPU durations in milliseconds.  Classes:
+ *   0 query preparation (validation, beta-mass), 1 accumulate, threshold
+ *   pass over the sampled tiles, 2 accumulate, scoring pass over every tile,
+ *   3 threshold selection, 4 finalize (top-gamma, rerank, top-k).
+ * Process-wide; reading with reset != 0 clears the totals.
+ */
+typedef struct {
+    int64_t launches[5];
+    double ms[5];
+} sindi_profile;
+
+sindi_status sindi_profile_enable(int32_t enable);
+sindi_status sindi_profile_read(sindi_profile *out, int32_t reset);
+
+/* Thread-local text of the last error of this thread ("" if none). */
+const char *sindi_last_error(void);
+
+/* Library version string. */
+const char *sindi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SINDI_H */

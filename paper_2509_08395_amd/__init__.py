@@ -1,0 +1,248 @@
+"""SINDI sparse maximum-inner-product search on MI355X (gfx950).
+
+A thin Python binding over the C ABI of ``libsindi.so`` (include/sindi.h):
+argument marshalling only.  Every step of the search path runs in the
+library's HIP kernels; PyTorch supplies device memory and the stream.
+Importing this package never falls back to CPU code: if the library is not
+built, :func:`_lib.load` raises.
+
+Method: arXiv 2509.08395 (SINDI) -- value-storing inverted lists cut into
+windows (Alg. 1, Sec. 3.3.1), mass-ratio pruning of documents and queries
+(Defs. 5-6, Alg. 3), coarse top-gamma over the pruned lists (Alg. 2) and an
+exact rerank from the unpruned vectors (Alg. 4).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import DTYPES, SindiError  # noqa: F401
+
+__all__ = ["Index", "DeviceCsr", "SindiScore", "SindiError", "version", "profile_enable",
+           "profile_read"]
+
+
+def version() -> str:
+    return _lib.load().sindi_version().decode()
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around every search kernel (see include/sindi.h)."""
+    _lib.check(_lib.load().sindi_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """{kernel class: (launches, total GPU ms)} since the last reset."""
+    p = _lib.SindiProfile()
+    _lib.check(_lib.load().sindi_profile_read(ctypes.byref(p), 1 if reset else 0))
+    return {name: (int(p.launches[i]), float(p.ms[i]))
+            for i, name in enumerate(_lib.PROFILE_CLASSES)}
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+class _HostCsr:
+    """A host CSR as the C struct (keeps the numpy arrays alive)."""
+
+    def __init__(self, csr):
+        self.indptr = np.ascontiguousarray(csr.indptr, dtype=np.int64)
+        self.indices = np.ascontiguousarray(csr.indices, dtype=np.int32)
+        self.values = np.ascontiguousarray(csr.values, dtype=np.float32)
+        self.n_rows = self.indptr.shape[0] - 1
+        self.n_cols = int(csr.n_cols)
+        self.nnz = int(self.indptr[-1]) if self.n_rows >= 0 else 0
+
+    def struct(self):
+        return _lib.SindiCsr(self.n_rows, self.n_cols, self.nnz, self.indptr.ctypes.data,
+                             self.indices.ctypes.data if self.nnz else None,
+                             self.values.ctypes.data if self.nnz else None, 0, 0)
+
+
+class DeviceCsr:
+    """A CSR whose arrays are torch tensors on the GPU."""
+
+    def __init__(self, indptr, indices, values, n_cols):
+        self.indptr, self.indices, self.values, self.n_cols = indptr, indices, values, int(n_cols)
+
+    @classmethod
+    def from_host(cls, csr, device="cuda"):
+        import torch
+        return cls(torch.as_tensor(np.asarray(csr.indptr, np.int64)).to(device),
+                   torch.as_tensor(np.asarray(csr.indices, np.int32)).to(device),
+                   torch.as_tensor(np.asarray(csr.values, np.float32)).to(device), csr.n_cols)
+
+    @property
+    def n_rows(self):
+        return int(self.indptr.shape[0]) - 1
+
+    @property
+    def nnz(self):
+        return int(self.indices.shape[0])
+
+    def struct(self):
+        for t, dt in ((self.indptr, "int64"), (self.indices, "int32"), (self.values, "float32")):
+            if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch." + dt:
+                raise ValueError(f"DeviceCsr arrays must be contiguous CUDA {dt} tensors")
+        return _lib.SindiCsr(self.n_rows, self.n_cols, self.nnz, self.indptr.data_ptr(),
+                             self.indices.data_ptr(), self.values.data_ptr(), 1, 0)
+
+
+def _query_struct(queries):
+    if isinstance(queries, DeviceCsr):
+        return queries.struct(), queries
+    h = _HostCsr(queries)
+    return h.struct(), h
+
+
+class Index:
+    """A SINDI index in device memory (Alg. 3: pruned window lists + unpruned corpus)."""
+
+    def __init__(self, corpus, alpha=1.0, window=100_000, value_dtype="f32", tile=0, stream=None):
+        lib = _lib.load()
+        h = _HostCsr(corpus)
+        params = _lib.SindiBuildParams(float(alpha), int(window), DTYPES[value_dtype], int(tile))
+        handle = ctypes.c_void_p()
+        _lib.check(lib.sindi_build(ctypes.byref(h.struct()), ctypes.byref(params),
+                                   _stream(stream), ctypes.byref(handle)))
+        self._h = handle
+        self.n_cols = h.n_cols
+        self.value_dtype = value_dtype
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().sindi_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = _lib.SindiIndexInfo()
+        _lib.check(_lib.load().sindi_index_get_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def export(self) -> dict:
+        """The device layout copied to host numpy arrays."""
+        inf = self.info()
+        nt, nc, npost = inf["n_tiles"], inf["n_cols"], inf["n_postings"]
+        tile_doc = np.empty(nt + 1, np.int64)
+        tile_post = np.empty(nt + 1, np.int64)
+        term_off = np.empty(nt * (nc + 1), np.uint32)
+        post_doc = np.empty(max(npost, 1), np.uint16)
+        vb = _lib.VALUE_BYTES[inf["value_dtype"]]
+        post_val = np.empty(max(npost, 1) * vb, np.uint8)
+        _lib.check(_lib.load().sindi_index_export(self._h, tile_doc.ctypes.data,
+                                                  tile_post.ctypes.data, term_off.ctypes.data,
+                                                  post_doc.ctypes.data, post_val.ctypes.data))
+        vt = {4: np.float32, 2: np.uint16}[vb]
+        return {"tile_doc": tile_doc, "tile_post": tile_post,
+                "term_off": term_off.reshape(nt, nc + 1), "post_doc": post_doc[:npost],
+                "post_val": post_val.view(vt)[:npost]}
+
+    def _run(self, fn, queries, k, beta, gamma, batch, cand_cap, sample_tiles, stream, out):
+        import torch
+        qs, keep = _query_struct(queries)
+        nq = qs.n_rows
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+            scores = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+        else:
+            ids, scores = out
+        params = _lib.SindiSearchParams(float(beta), int(gamma), int(batch), int(cand_cap),
+                                        int(sample_tiles))
+        _lib.check(fn(self._h, ctypes.byref(qs), int(k), ctypes.byref(params),
+                      ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(scores.data_ptr()),
+                      _stream(stream)))
+        del keep
+        return ids, scores
+
+    def search(self, queries, k, beta=1.0, gamma=0, batch=0, cand_cap=0, sample_tiles=0,
+               stream=None, out=None):
+        """Alg. 4: (ids int64 [n, k], scores float32 [n, k]) as CUDA tensors."""
+        return self._run(_lib.load().sindi_search, queries, k, beta, gamma, batch, cand_cap,
+                         sample_tiles, stream, out)
+
+    def search_coarse(self, queries, k, beta=1.0, batch=0, cand_cap=0, sample_tiles=0,
+                      stream=None, out=None):
+        """Alg. 2 over the (pruned) index: coarse top-k, no rerank."""
+        return self._run(_lib.load().sindi_search_coarse, queries, k, beta, 0, batch, cand_cap,
+                         sample_tiles, stream, out)
+
+    def score(self, queries: DeviceCsr, cand, stream=None):
+        """delta(q_b, x_c) for cand [n_q, n_cand] (int64 CUDA) -> float32 [n_q, n_cand]."""
+        import torch
+        cand = cand.contiguous()
+        out = torch.empty(cand.shape, dtype=torch.float32, device="cuda")
+        qs = queries.struct()
+        _lib.check(_lib.load().sindi_score_forward(self._h, ctypes.byref(qs),
+                                                   ctypes.c_void_p(cand.data_ptr()),
+                                                   int(cand.shape[1]),
+                                                   ctypes.c_void_p(out.data_ptr()),
+                                                   _stream(stream)))
+        return out
+
+    def score_backward(self, queries: DeviceCsr, cand, grad, grad_query=None, grad_doc=None,
+                       stream=None):
+        cand = cand.contiguous()
+        grad = grad.contiguous().float()
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        qs = queries.struct()
+        _lib.check(_lib.load().sindi_score_backward(self._h, ctypes.byref(qs), ptr(cand),
+                                                    int(cand.shape[1]), ptr(grad),
+                                                    ptr(grad_query), ptr(grad_doc),
+                                                    _stream(stream)))
+
+
+def _make_score_fn():
+    import torch
+
+    class SindiScore(torch.autograd.Function):
+        """s[b, c] = delta(q_b, x_{cand[b, c]}) with hand-written HIP forward and backward.
+
+        Inputs: query values (requires_grad), document values of the corpus the index
+        was built from (requires_grad; the index holds its own copy of these values,
+        so they must not change after the build), the index, the query CSR structure
+        (indptr, indices) and candidate ids [n_q, n_cand].
+        """
+
+        @staticmethod
+        def forward(ctx, q_values, doc_values, index, q_indptr, q_indices, cand):
+            qs = DeviceCsr(q_indptr, q_indices, q_values.detach().contiguous(), index.n_cols)
+            ctx.index, ctx.qs, ctx.cand = index, qs, cand
+            ctx.doc_shape = doc_values.shape
+            ctx.needs = (ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+            return index.score(qs, cand)
+
+        @staticmethod
+        def backward(ctx, grad):
+            gq = torch.zeros_like(ctx.qs.values) if ctx.needs[0] else None
+            gx = (torch.zeros(ctx.doc_shape, dtype=torch.float32, device="cuda")
+                  if ctx.needs[1] else None)
+            ctx.index.score_backward(ctx.qs, ctx.cand, grad, gq, gx)
+            return gq, gx, None, None, None, None
+
+    return SindiScore
+
+
+class _LazyScore:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _LazyScore._fn is None:
+            _LazyScore._fn = _make_score_fn()
+        return getattr(_LazyScore._fn, name)
+
+
+SindiScore = _LazyScore()

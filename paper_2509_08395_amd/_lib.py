@@ -1,0 +1,105 @@
+"""ctypes declarations of the C ABI in include/sindi.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsindi.so")
+
+SINDI_OK, SINDI_E_INVALID, SINDI_E_RANGE, SINDI_E_OOM, SINDI_E_HIP, SINDI_E_INTERNAL = (
+    0, -1, -2, -3, -4, -6)
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+VALUE_BYTES = {0: 4, 1: 2, 2: 2}
+
+P = ctypes.c_void_p
+
+
+class SindiCsr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("indptr", P), ("indices", P), ("values", P), ("on_device", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
+
+
+class SindiBuildParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("window", ctypes.c_int64),
+                ("value_dtype", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
+class SindiSearchParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("gamma", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("cand_cap", ctypes.c_int32), ("sample_tiles", ctypes.c_int32)]
+
+
+class SindiIndexInfo(ctypes.Structure):
+    _fields_ = [("n_docs", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("n_postings", ctypes.c_int64), ("window", ctypes.c_int64),
+                ("n_windows", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+                ("tile_max", ctypes.c_int32), ("value_dtype", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+class SindiProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("ms", ctypes.c_double * 5)]
+
+
+PROFILE_CLASSES = ("query_prep", "accumulate_threshold", "accumulate_score", "threshold_select",
+                   "finalize")
+
+EXPORTS = ("sindi_build", "sindi_index_free", "sindi_index_get_info", "sindi_index_export",
+           "sindi_search", "sindi_search_coarse", "sindi_score_forward", "sindi_score_backward",
+           "sindi_profile_enable", "sindi_profile_read", "sindi_last_error", "sindi_version")
+
+
+class SindiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sindi error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libsindi.so (after torch, so both share one HIP runtime).  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  -- loads torch's HIP runtime first
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python -m paper_2509_08395_amd._build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    I32, I64 = ctypes.c_int32, ctypes.c_int64
+    lib.sindi_build.argtypes = [ctypes.POINTER(SindiCsr), ctypes.POINTER(SindiBuildParams), P,
+                                ctypes.POINTER(P)]
+    lib.sindi_index_free.argtypes = [P]
+    lib.sindi_index_free.restype = None
+    lib.sindi_index_get_info.argtypes = [P, ctypes.POINTER(SindiIndexInfo)]
+    lib.sindi_index_export.argtypes = [P, P, P, P, P, P]
+    for f in (lib.sindi_search, lib.sindi_search_coarse):
+        f.argtypes = [P, ctypes.POINTER(SindiCsr), I32, ctypes.POINTER(SindiSearchParams), P, P, P]
+    lib.sindi_score_forward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P]
+    lib.sindi_score_backward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P, P, P]
+    for f in (lib.sindi_build, lib.sindi_index_get_info, lib.sindi_index_export,
+              lib.sindi_search, lib.sindi_search_coarse, lib.sindi_score_forward,
+              lib.sindi_score_backward):
+        f.restype = ctypes.c_int
+    lib.sindi_profile_enable.argtypes = [I32]
+    lib.sindi_profile_enable.restype = ctypes.c_int
+    lib.sindi_profile_read.argtypes = [ctypes.POINTER(SindiProfile), I32]
+    lib.sindi_profile_read.restype = ctypes.c_int
+    lib.sindi_last_error.restype = ctypes.c_char_p
+    lib.sindi_last_error.argtypes = []
+    lib.sindi_version.restype = ctypes.c_char_p
+    lib.sindi_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def check(code):
+    if code != SINDI_OK:
+        raise SindiError(code, load().sindi_last_error().decode(errors="replace"))

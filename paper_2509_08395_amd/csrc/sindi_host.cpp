@@ -1,0 +1,772 @@
+// Host side of the SINDI library: input validation, mass-ratio pruning,
+// window/tile layout of the inverted lists, device upload, and the search
+// pipeline that drives the gfx950 kernels.  Implements include/sindi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "sindi.h"
+#include "sindi_internal.h"
+
+using namespace sindi;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_err;
+
+sindi_status fail(sindi_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) return fail(SINDI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int host_threads()
+{
+    const char *env = getenv("OMP_NUM_THREADS");
+    int n = env ? atoi(env) : 0;
+    if (n <= 0) n = (int)std::thread::hardware_concurrency();
+    return n < 1 ? 1 : (n > 64 ? 64 : n);
+}
+
+// Run fn(lo, hi) over [0, n) in contiguous slices on the host threads.
+template <typename F>
+void parallel_for(int64_t n, F fn)
+{
+    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(n / 1024, 1));
+    if (nt <= 1) {
+        fn((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t step = (n + nt - 1) / nt;
+    for (int i = 0; i < nt; ++i) {
+        const int64_t lo = i * step, hi = std::min(n, lo + step);
+        if (lo >= hi) break;
+        th.emplace_back([=] { fn(lo, hi); });
+    }
+    for (auto &t : th) t.join();
+}
+
+// Grow-only device buffer.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        size_t want = n < 256 ? 256 : n;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = want;
+        return hipSuccess;
+    }
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// FP32 -> FP16 / BF16, round to nearest even.
+uint16_t to_f16(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+uint16_t to_bf16(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ------------------------------------------------------------------ profiling
+struct Profiler {
+    std::mutex mu;
+    std::atomic<bool> on{false};
+    struct Rec {
+        int cat;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    int64_t n[5] = {0, 0, 0, 0, 0};
+    double ms[5] = {0, 0, 0, 0, 0};
+};
+Profiler g_prof;
+
+enum { kProfPrep = 0, kProfSample = 1, kProfScore = 2, kProfTheta = 3, kProfFinal = 4 };
+
+// Launch through `fn`, bracketed by events on `s` while profiling is on.
+template <typename F>
+hipError_t timed(int cat, hipStream_t s, F fn)
+{
+    if (!g_prof.on.load(std::memory_order_relaxed)) return fn();
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    g_prof.pending.push_back({cat, a, b});
+    return e;
+}
+
+constexpr int32_t kDefaultTile = 4096;
+constexpr int32_t kDefaultBatch = 4;
+constexpr int32_t kDefaultCandCap = 32768;
+constexpr int32_t kDefaultSampleTiles = 32;
+constexpr int32_t kDefaultGamma = 500;
+constexpr size_t kCandBudget = size_t(2) << 30;  // candidate buffer bytes per pass
+
+}  // namespace
+
+// ------------------------------------------------------------------ index
+struct sindi_index {
+    int64_t n_docs = 0, n_cols = 0, nnz = 0, n_post = 0, window = 0, n_windows = 0, n_tiles = 0;
+    int32_t tile_max = 0, tile_stride = 0, dtype = 0;
+    double alpha = 1.0;
+    int device = 0;
+    int64_t max_lds = 0;
+    std::vector<int64_t> h_tile_doc;
+    DBuf indptr, indices, values, tile_doc, tile_post, term_off, post_doc, post_val;
+    // search workspace, guarded by mu
+    std::mutex mu;
+    DBuf q_ptr, q_idx, q_val, ct, cw, cn, sabs, err, status, slot_q, maxima, theta, count, cand;
+
+    DevIndex dev() const
+    {
+        DevIndex d;
+        d.n_docs = n_docs;
+        d.n_cols = n_cols;
+        d.n_tiles = n_tiles;
+        d.tile_stride = tile_stride;
+        d.value_dtype = dtype;
+        d.tile_doc = tile_doc.as<int64_t>();
+        d.tile_post = tile_post.as<int64_t>();
+        d.term_off = term_off.as<uint32_t>();
+        d.post_doc = post_doc.as<uint16_t>();
+        d.post_val = post_val.p;
+        d.indptr = indptr.as<int64_t>();
+        d.indices = indices.as<int32_t>();
+        d.values = values.as<float>();
+        d.nnz = nnz;
+        return d;
+    }
+    int64_t device_bytes() const
+    {
+        return (int64_t)(indptr.bytes + indices.bytes + values.bytes + tile_doc.bytes +
+                         tile_post.bytes + term_off.bytes + post_doc.bytes + post_val.bytes);
+    }
+};
+
+namespace {
+
+// Structural check of a host CSR (Def. 1: each row a set of non-zero
+// entries over [0, n_cols); ids strictly ascending; finite values).
+sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max_row)
+{
+    if (m->n_rows < 0 || m->n_cols < 1 || m->n_cols > INT32_MAX || m->nnz < 0)
+        return fail(SINDI_E_INVALID, "%s: bad shape (rows %lld, cols %lld, nnz %lld)", what,
+                    (long long)m->n_rows, (long long)m->n_cols, (long long)m->nnz);
+    if (!m->indptr || (m->nnz > 0 && (!m->indices || !m->values)))
+        return fail(SINDI_E_INVALID, "%s: null array", what);
+    if (m->indptr[0] != 0 || m->indptr[m->n_rows] != m->nnz)
+        return fail(SINDI_E_INVALID, "%s: indptr[0] must be 0 and indptr[n_rows] == nnz", what);
+    std::atomic<int64_t> bad_row{-1};
+    std::atomic<int> bad_kind{0};
+    parallel_for(m->n_rows, [&](int64_t lo, int64_t hi) {
+        for (int64_t r = lo; r < hi && bad_row.load(std::memory_order_relaxed) < 0; ++r) {
+            const int64_t a = m->indptr[r], b = m->indptr[r + 1];
+            int kind = 0;
+            if (b < a || a < 0 || b > m->nnz) kind = 1;
+            else if (max_row > 0 && b - a > max_row) kind = 5;
+            else
+                for (int64_t e = a; e < b && !kind; ++e) {
+                    const int32_t id = m->indices[e];
+                    if (id < 0 || id >= m->n_cols) kind = 2;
+                    else if (e + 1 < b && m->indices[e + 1] <= id) kind = 3;
+                    else if (!std::isfinite(m->values[e])) kind = 4;
+                }
+            if (kind) {
+                int64_t expect = -1;
+                if (bad_row.compare_exchange_strong(expect, r)) bad_kind = kind;
+            }
+        }
+    });
+    if (bad_row >= 0) {
+        static const char *msg[] = {"", "row pointers not monotone", "term id out of range",
+                                    "term ids not strictly ascending (duplicate or unsorted)",
+                                    "non-finite value", "row has too many entries"};
+        return fail(SINDI_E_INVALID, "%s: row %lld: %s", what, (long long)bad_row.load(),
+                    msg[bad_kind.load()]);
+    }
+    return SINDI_OK;
+}
+
+// Def. 6 for one row: keep[e] = 1 for the entries of the alpha-mass
+// subvector.  Entries ranked by |x| descending, equal |x| by ascending term
+// id; prefix sums of |x| in FP64 in that order; r = first prefix reaching
+// alpha * mass, mass being the full sum in the same order.  Explicit zeros
+// are not entries and are never kept.
+void mass_ratio_row(const int32_t *idx, const float *val, int64_t n, double alpha,
+                    std::vector<int64_t> &order, uint8_t *keep)
+{
+    order.clear();
+    for (int64_t e = 0; e < n; ++e) {
+        keep[e] = 0;
+        if (val[e] != 0.0f) order.push_back(e);
+    }
+    if (order.empty()) return;
+    if (alpha >= 1.0) {
+        for (int64_t e : order) keep[e] = 1;
+        return;
+    }
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        const float ax = std::fabs(val[x]), ay = std::fabs(val[y]);
+        return ax > ay || (ax == ay && idx[x] < idx[y]);
+    });
+    double mass = 0.0;
+    for (int64_t e : order) mass += (double)std::fabs(val[e]);
+    const double thr = alpha * mass;
+    double run = 0.0;
+    size_t r = 0;
+    while (r < order.size()) {
+        run += (double)std::fabs(val[order[r]]);
+        ++r;
+        if (run >= thr) break;
+    }
+    for (size_t t = 0; t < r; ++t) keep[order[t]] = 1;
+}
+
+sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStream_t s,
+                        sindi_index **out)
+{
+    if (!c || !p || !out) return fail(SINDI_E_INVALID, "sindi_build: null argument");
+    if (c->on_device) return fail(SINDI_E_INVALID, "sindi_build: corpus must be host memory");
+    if (!(p->alpha > 0.0 && p->alpha <= 1.0))
+        return fail(SINDI_E_INVALID, "sindi_build: alpha must be in (0, 1], got %g", p->alpha);
+    if (p->window < 1) return fail(SINDI_E_INVALID, "sindi_build: window must be >= 1");
+    if (p->value_dtype < 0 || p->value_dtype > 2)
+        return fail(SINDI_E_INVALID, "sindi_build: unknown value dtype %d", p->value_dtype);
+    const int32_t tile_req = p->tile ? p->tile : kDefaultTile;
+    if (tile_req < 1 || tile_req > 65536)
+        return fail(SINDI_E_INVALID, "sindi_build: tile must be in [1, 65536]");
+    if (c->n_rows >= (int64_t)0xFFFFFFFF)
+        return fail(SINDI_E_INVALID, "sindi_build: too many documents");
+    sindi_status st = validate_host_csr(c, "corpus", 0);
+    if (st != SINDI_OK) return st;
+
+    sindi_index *ix = new (std::nothrow) sindi_index();
+    if (!ix) return fail(SINDI_E_OOM, "sindi_build: host allocation failed");
+    std::unique_ptr<sindi_index> guard(ix);
+    HIP_TRY(hipGetDevice(&ix->device));
+    int lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
+    ix->max_lds = lds;
+    const int64_t nd = c->n_rows, nc = c->n_cols;
+    ix->n_docs = nd;
+    ix->n_cols = nc;
+    ix->nnz = c->nnz;
+    ix->alpha = p->alpha;
+    ix->window = p->window;
+    ix->dtype = p->value_dtype;
+    ix->n_windows = nd ? (nd + p->window - 1) / p->window : 0;
+
+    // windows of lambda documents (Sec. 3.3.1), each split into equal tiles
+    std::vector<int64_t> tile_doc{0};
+    int32_t tmax = 0;
+    for (int64_t w = 0; w < ix->n_windows; ++w) {
+        const int64_t w0 = w * p->window, wl = std::min(p->window, nd - w0);
+        const int64_t nt = (wl + tile_req - 1) / tile_req;
+        const int64_t base = wl / nt, extra = wl % nt;
+        int64_t d = w0;
+        for (int64_t i = 0; i < nt; ++i) {
+            const int64_t l = base + (i < extra ? 1 : 0);
+            d += l;
+            tile_doc.push_back(d);
+            tmax = std::max<int32_t>(tmax, (int32_t)l);
+        }
+    }
+    const int64_t n_tiles = (int64_t)tile_doc.size() - 1;
+    ix->n_tiles = n_tiles;
+    ix->tile_max = tmax;
+    ix->tile_stride = std::max<int32_t>(4, (tmax + 3) / 4 * 4);
+    if ((int64_t)ix->tile_stride * 4 + (5 * kEntryBlock + 1) * 4 > ix->max_lds)
+        return fail(SINDI_E_INVALID, "sindi_build: tile of %d documents exceeds on-chip memory",
+                    tmax);
+
+    // Alg. 3 line 3: alpha-mass subvector of every document
+    std::vector<uint8_t> keep((size_t)c->nnz);
+    parallel_for(nd, [&](int64_t lo, int64_t hi) {
+        std::vector<int64_t> order;
+        for (int64_t r = lo; r < hi; ++r) {
+            const int64_t a = c->indptr[r];
+            mass_ratio_row(c->indices + a, c->values + a, c->indptr[r + 1] - a, p->alpha, order,
+                           keep.data() + a);
+        }
+    });
+
+    // Alg. 1 per tile: counts of every (tile, term) list, then offsets
+    const size_t stride = (size_t)nc + 1;
+    std::vector<uint32_t> term_off((size_t)n_tiles * stride, 0u);
+    std::vector<int64_t> tile_post((size_t)n_tiles + 1, 0);
+    std::atomic<int> range_bad{0};
+    parallel_for(n_tiles, [&](int64_t lo, int64_t hi) {
+        for (int64_t t = lo; t < hi; ++t) {
+            uint32_t *cnt = term_off.data() + (size_t)t * stride;
+            for (int64_t i = tile_doc[t]; i < tile_doc[t + 1]; ++i)
+                for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e)
+                    if (keep[e]) {
+                        cnt[c->indices[e]]++;
+                        if (p->value_dtype == SINDI_F16 && std::fabs(c->values[e]) > 65504.0f)
+                            range_bad = 1;
+                        if (p->value_dtype == SINDI_BF16 &&
+                            std::isinf(__builtin_bit_cast(float, (uint32_t)to_bf16(c->values[e]) << 16)))
+                            range_bad = 1;
+                    }
+            uint32_t acc = 0;
+            for (int64_t j = 0; j < nc; ++j) {
+                const uint32_t v = cnt[j];
+                cnt[j] = acc;
+                acc += v;
+            }
+            cnt[nc] = acc;
+            tile_post[t + 1] = acc;
+        }
+    });
+    if (range_bad) return fail(SINDI_E_RANGE, "sindi_build: a kept value overflows the storage type");
+    for (int64_t t = 0; t < n_tiles; ++t) tile_post[t + 1] += tile_post[t];
+    const int64_t n_post = tile_post[n_tiles];
+    ix->n_post = n_post;
+    const int64_t n_pad = (n_post + 3) / 4 * 4 + 8;
+    const size_t vbytes = p->value_dtype == SINDI_F32 ? 4 : 2;
+    std::vector<uint16_t> post_doc((size_t)n_pad, 0);
+    std::vector<uint8_t> post_val((size_t)n_pad * vbytes, 0);
+    parallel_for(n_tiles, [&](int64_t lo, int64_t hi) {
+        std::vector<uint32_t> fill(stride);
+        for (int64_t t = lo; t < hi; ++t) {
+            memcpy(fill.data(), term_off.data() + (size_t)t * stride, stride * sizeof(uint32_t));
+            const int64_t P0 = tile_post[t], d0 = tile_doc[t];
+            for (int64_t i = tile_doc[t]; i < tile_doc[t + 1]; ++i)
+                for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e) {
+                    if (!keep[e]) continue;
+                    const int64_t pos = P0 + fill[c->indices[e]]++;
+                    post_doc[pos] = (uint16_t)(i - d0);
+                    const float v = c->values[e];
+                    if (p->value_dtype == SINDI_F32) memcpy(&post_val[pos * 4], &v, 4);
+                    else {
+                        const uint16_t h = p->value_dtype == SINDI_F16 ? to_f16(v) : to_bf16(v);
+                        memcpy(&post_val[pos * 2], &h, 2);
+                    }
+                }
+        }
+    });
+
+    // upload: unpruned corpus (Alg. 3 returns D too) and the tiled lists
+    auto up = [&](DBuf &b, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = b.ensure(bytes);
+        if (e != hipSuccess) return e;
+        if (bytes) e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s);
+        return e;
+    };
+    auto up_or_fail = [&](DBuf &b, const void *src, size_t bytes, const char *what) -> sindi_status {
+        hipError_t e = up(b, src, bytes);
+        if (e == hipErrorOutOfMemory) return fail(SINDI_E_OOM, "sindi_build: device allocation of %s failed", what);
+        if (e != hipSuccess) return fail(SINDI_E_HIP, "sindi_build: upload of %s: %s", what, hipGetErrorString(e));
+        return SINDI_OK;
+    };
+    if ((st = up_or_fail(ix->indptr, c->indptr, (size_t)(nd + 1) * 8, "indptr")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->indices, c->indices, (size_t)c->nnz * 4, "indices")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->values, c->values, (size_t)c->nnz * 4, "values")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->tile_doc, tile_doc.data(), tile_doc.size() * 8, "tile_doc")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->tile_post, tile_post.data(), tile_post.size() * 8, "tile_post")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->term_off, term_off.data(), term_off.size() * 4, "term offsets")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->post_doc, post_doc.data(), post_doc.size() * 2, "posting ids")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->post_val, post_val.data(), post_val.size(), "posting values")) != SINDI_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    ix->h_tile_doc = std::move(tile_doc);
+    *out = guard.release();
+    return SINDI_OK;
+}
+
+// ------------------------------------------------------------------ search
+int pick_batch(const sindi_index *ix, int32_t req)
+{
+    int b = req ? req : kDefaultBatch;
+    if (b != 1 && b != 2 && b != 4 && b != 8) return -1;
+    while (b > 1 && (int64_t)b * ix->tile_stride * 4 + (5 * kEntryBlock + 1) * 4 > ix->max_lds) b >>= 1;
+    return b;
+}
+
+sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
+                         const sindi_search_params *pp, int64_t *out_ids, float *out_scores,
+                         hipStream_t s, bool rerank, const char *fn)
+{
+    if (!ix || !qc || !out_ids || !out_scores) return fail(SINDI_E_INVALID, "%s: null argument", fn);
+    sindi_search_params p{};
+    if (pp) p = *pp;
+    const double beta = p.beta == 0.0 ? 1.0 : p.beta;
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SINDI_E_INVALID, "%s: beta must be in (0, 1]", fn);
+    if (k < 1 || k > kGammaMax) return fail(SINDI_E_INVALID, "%s: k must be in [1, %d]", fn, kGammaMax);
+    int32_t gamma = rerank ? (p.gamma ? p.gamma : std::max(k, kDefaultGamma)) : k;
+    if (gamma < k || gamma > kGammaMax)
+        return fail(SINDI_E_INVALID, "%s: gamma must be in [k, %d]", fn, kGammaMax);
+    if (qc->n_cols != ix->n_cols)
+        return fail(SINDI_E_INVALID, "%s: queries have %lld columns, index has %lld", fn,
+                    (long long)qc->n_cols, (long long)ix->n_cols);
+    const int batch = pick_batch(ix, p.batch);
+    if (batch < 1) return fail(SINDI_E_INVALID, "%s: batch must be 1, 2, 4 or 8", fn);
+    if (qc->n_rows < 0 || qc->nnz < 0) return fail(SINDI_E_INVALID, "%s: bad query shape", fn);
+    const int64_t nq = qc->n_rows;
+    if (nq == 0) return SINDI_OK;
+    if (nq > INT32_MAX / 2) return fail(SINDI_E_INVALID, "%s: too many queries", fn);
+    std::lock_guard<std::mutex> lock(ix->mu);
+
+    DevQueries dq{nq, qc->nnz, qc->indptr, qc->indices, qc->values};
+    if (!qc->on_device) {
+        sindi_status st = validate_host_csr(qc, "queries", kQueryHash / 2);
+        if (st != SINDI_OK) return st;
+        HIP_TRY(ix->q_ptr.ensure((size_t)(nq + 1) * 8));
+        HIP_TRY(ix->q_idx.ensure((size_t)qc->nnz * 4 + 4));
+        HIP_TRY(ix->q_val.ensure((size_t)qc->nnz * 4 + 4));
+        HIP_TRY(hipMemcpyAsync(ix->q_ptr.p, qc->indptr, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, s));
+        if (qc->nnz) {
+            HIP_TRY(hipMemcpyAsync(ix->q_idx.p, qc->indices, (size_t)qc->nnz * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(ix->q_val.p, qc->values, (size_t)qc->nnz * 4, hipMemcpyHostToDevice, s));
+        }
+        dq.indptr = ix->q_ptr.as<int64_t>();
+        dq.indices = ix->q_idx.as<int32_t>();
+        dq.values = ix->q_val.as<float>();
+    } else if (!qc->indptr || (qc->nnz > 0 && (!qc->indices || !qc->values))) {
+        return fail(SINDI_E_INVALID, "%s: null query array", fn);
+    }
+
+    // coarse query terms (beta-mass) and device-side validation
+    HIP_TRY(ix->ct.ensure((size_t)qc->nnz * 4 + 4));
+    HIP_TRY(ix->cw.ensure((size_t)qc->nnz * 4 + 4));
+    HIP_TRY(ix->cn.ensure((size_t)nq * 4));
+    HIP_TRY(ix->sabs.ensure(beta < 1.0 ? (size_t)qc->nnz * 8 + 8 : 8));
+    HIP_TRY(ix->err.ensure(4));
+    HIP_TRY(ix->status.ensure((size_t)nq * 4));
+    HIP_TRY(launch_fill_u32(ix->err.as<uint32_t>(), 1, 0u, s));
+    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>()};
+    HIP_TRY(timed(kProfPrep, s, [&] { return launch_query_prep(dq, ix->n_cols, beta, dc, ix->sabs.as<double>(), ix->err.as<int32_t>(), s); }));
+    int32_t qerr = 0;
+    HIP_TRY(hipMemcpyAsync(&qerr, ix->err.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (qerr)
+        return fail(SINDI_E_INVALID,
+                    "%s: malformed query rows (flags 0x%x: 1 row pointers, 2 term id range, 4 order, "
+                    "8 non-finite, 16 more than %d entries)",
+                    fn, qerr, kQueryHash / 2);
+
+    const DevIndex dix = ix->dev();
+    if (ix->n_docs == 0) {
+        HIP_TRY(launch_fill_f32(out_scores, nq * k, -INFINITY, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(out_ids), 2 * nq * k, 0xFFFFFFFFu, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SINDI_OK;
+    }
+    const int32_t need = (int32_t)std::min<int64_t>(gamma, ix->n_docs);
+
+    // candidate threshold: sample tiles first, or keep every document
+    int64_t cap = p.cand_cap > 0 ? p.cand_cap : kDefaultCandCap;
+    cap = std::max<int64_t>(cap, need);
+    bool keep_all = p.sample_tiles < 0 || ix->n_docs <= cap;
+    if (keep_all) cap = ix->n_docs;
+    const int32_t n_sample =
+        keep_all ? 0 : (int32_t)std::min<int64_t>(ix->n_tiles, p.sample_tiles ? p.sample_tiles : kDefaultSampleTiles);
+    int64_t rank = 0, n_max = 0;
+    if (!keep_all) {
+        int64_t sampled = 0;
+        const std::vector<int64_t> &td = ix->h_tile_doc;
+        for (int64_t i = 0; i < n_sample; ++i) {
+            const int64_t t = i * ix->n_tiles / n_sample;
+            sampled += td[t + 1] - td[t];
+        }
+        const double f = (double)sampled / (double)ix->n_docs;
+        n_max = (int64_t)n_sample * kAccThreads;
+        rank = std::min<int64_t>(n_max, (int64_t)std::ceil(2.0 * need * f) + 8);
+    }
+    const int64_t group = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(kCandBudget / ((size_t)cap * 8))));
+    HIP_TRY(ix->cand.ensure((size_t)group * cap * 8));
+    HIP_TRY(ix->count.ensure((size_t)group * 4));
+    HIP_TRY(ix->theta.ensure((size_t)group * 4));
+    HIP_TRY(ix->slot_q.ensure((size_t)std::max<int64_t>(group, 1) * 4));
+    if (!keep_all) HIP_TRY(ix->maxima.ensure((size_t)group * n_max * 4));
+
+    std::vector<int32_t> rows((size_t)group);
+    for (int64_t g0 = 0; g0 < nq; g0 += group) {
+        const int32_t ns = (int32_t)std::min<int64_t>(group, nq - g0);
+        for (int32_t i = 0; i < ns; ++i) rows[i] = (int32_t)(g0 + i);
+        HIP_TRY(hipMemcpyAsync(ix->slot_q.p, rows.data(), (size_t)ns * 4, hipMemcpyHostToDevice, s));
+        if (keep_all) {
+            HIP_TRY(launch_fill_f32(ix->theta.as<float>(), ns, -INFINITY, s));
+        } else {
+            HIP_TRY(timed(kProfSample, s, [&] {
+                return launch_accumulate(dix, dq, dc, batch, true, ix->slot_q.as<int32_t>(), ns, n_sample,
+                                         ix->maxima.as<float>(), nullptr, nullptr, nullptr, 0, s);
+            }));
+            HIP_TRY(timed(kProfTheta, s, [&] {
+                return launch_theta(ix->maxima.as<float>(), n_max, rank, ns, ix->theta.as<float>(), s);
+            }));
+        }
+        HIP_TRY(launch_fill_u32(ix->count.as<uint32_t>(), ns, 0u, s));
+        HIP_TRY(timed(kProfScore, s, [&] {
+            return launch_accumulate(dix, dq, dc, batch, false, ix->slot_q.as<int32_t>(), ns, 0, nullptr,
+                                     ix->theta.as<float>(), ix->count.as<uint32_t>(),
+                                     ix->cand.as<uint64_t>(), cap, s);
+        }));
+        HIP_TRY(timed(kProfFinal, s, [&] {
+            return launch_finalize(dix, dq, ix->slot_q.as<int32_t>(), ns, ix->count.as<uint32_t>(),
+                                   ix->cand.as<uint64_t>(), cap, need, k, rerank, out_ids, out_scores,
+                                   ix->status.as<int32_t>(), s);
+        }));
+        // the host copy of rows[] must outlive the async upload above
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    std::vector<int32_t> status((size_t)nq);
+    HIP_TRY(hipMemcpyAsync(status.data(), ix->status.p, (size_t)nq * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> retry;
+    for (int64_t q = 0; q < nq; ++q)
+        if (status[q] != kSlotOk) retry.push_back((int32_t)q);
+    if (!retry.empty()) {
+        // threshold missed gamma candidates or overflowed: keep every document
+        const int64_t cap_all = ix->n_docs;
+        const int64_t g_all = std::max<int64_t>(1, (int64_t)(kCandBudget / ((size_t)cap_all * 8)));
+        const int64_t gsz = std::min<int64_t>(g_all, (int64_t)retry.size());
+        HIP_TRY(ix->cand.ensure((size_t)gsz * cap_all * 8));
+        HIP_TRY(ix->count.ensure((size_t)gsz * 4));
+        HIP_TRY(ix->theta.ensure((size_t)gsz * 4));
+        HIP_TRY(ix->slot_q.ensure((size_t)gsz * 4));
+        for (size_t g0 = 0; g0 < retry.size(); g0 += (size_t)gsz) {
+            const int32_t ns = (int32_t)std::min<size_t>((size_t)gsz, retry.size() - g0);
+            HIP_TRY(hipMemcpyAsync(ix->slot_q.p, retry.data() + g0, (size_t)ns * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_fill_f32(ix->theta.as<float>(), ns, -INFINITY, s));
+            HIP_TRY(launch_fill_u32(ix->count.as<uint32_t>(), ns, 0u, s));
+            HIP_TRY(timed(kProfScore, s, [&] {
+                return launch_accumulate(dix, dq, dc, 1, false, ix->slot_q.as<int32_t>(), ns, 0, nullptr,
+                                         ix->theta.as<float>(), ix->count.as<uint32_t>(),
+                                         ix->cand.as<uint64_t>(), cap_all, s);
+            }));
+            HIP_TRY(timed(kProfFinal, s, [&] {
+                return launch_finalize(dix, dq, ix->slot_q.as<int32_t>(), ns, ix->count.as<uint32_t>(),
+                                       ix->cand.as<uint64_t>(), cap_all, need, k, rerank, out_ids,
+                                       out_scores, ix->status.as<int32_t>(), s);
+            }));
+        }
+        HIP_TRY(hipMemcpyAsync(status.data(), ix->status.p, (size_t)nq * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int32_t q : retry)
+            if (status[q] != kSlotOk) return fail(SINDI_E_INTERNAL, "%s: query %d unresolved", fn, q);
+    }
+    return SINDI_OK;
+}
+
+sindi_status check_dev_queries(sindi_index *ix, const sindi_csr *qc, const char *fn, hipStream_t s)
+{
+    if (!qc->on_device) return fail(SINDI_E_INVALID, "%s: queries must be device memory", fn);
+    if (qc->n_cols != ix->n_cols) return fail(SINDI_E_INVALID, "%s: column count mismatch", fn);
+    if (qc->n_rows < 0 || qc->nnz < 0) return fail(SINDI_E_INVALID, "%s: bad query shape", fn);
+    if (qc->n_rows == 0) return SINDI_OK;
+    DevQueries dq{qc->n_rows, qc->nnz, qc->indptr, qc->indices, qc->values};
+    HIP_TRY(ix->ct.ensure((size_t)qc->nnz * 4 + 4));
+    HIP_TRY(ix->cw.ensure((size_t)qc->nnz * 4 + 4));
+    HIP_TRY(ix->cn.ensure((size_t)qc->n_rows * 4));
+    HIP_TRY(ix->err.ensure(4));
+    HIP_TRY(launch_fill_u32(ix->err.as<uint32_t>(), 1, 0u, s));
+    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>()};
+    HIP_TRY(launch_query_prep(dq, ix->n_cols, 1.0, dc, nullptr, ix->err.as<int32_t>(), s));
+    int32_t qerr = 0;
+    HIP_TRY(hipMemcpyAsync(&qerr, ix->err.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (qerr) return fail(SINDI_E_INVALID, "%s: malformed query rows (flags 0x%x)", fn, qerr);
+    return SINDI_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+sindi_status sindi_build(const sindi_csr *corpus, const sindi_build_params *params, void *stream,
+                         sindi_index **out)
+{
+    try {
+        return build_impl(corpus, params, (hipStream_t)stream, out);
+    } catch (const std::bad_alloc &) {
+        return fail(SINDI_E_OOM, "sindi_build: host allocation failed");
+    } catch (...) {
+        return fail(SINDI_E_INTERNAL, "sindi_build: unexpected exception");
+    }
+}
+
+void sindi_index_free(sindi_index *idx) { delete idx; }
+
+sindi_status sindi_index_get_info(const sindi_index *ix, sindi_index_info *o)
+{
+    if (!ix || !o) return fail(SINDI_E_INVALID, "sindi_index_get_info: null argument");
+    o->n_docs = ix->n_docs;
+    o->n_cols = ix->n_cols;
+    o->nnz = ix->nnz;
+    o->n_postings = ix->n_post;
+    o->window = ix->window;
+    o->n_windows = ix->n_windows;
+    o->n_tiles = ix->n_tiles;
+    o->tile_max = ix->tile_max;
+    o->value_dtype = ix->dtype;
+    o->alpha = ix->alpha;
+    o->device_bytes = ix->device_bytes();
+    return SINDI_OK;
+}
+
+sindi_status sindi_index_export(const sindi_index *ix, int64_t *tile_doc, int64_t *tile_post,
+                                uint32_t *term_off, uint16_t *post_doc, void *post_val)
+{
+    if (!ix) return fail(SINDI_E_INVALID, "sindi_index_export: null index");
+    const size_t vb = ix->dtype == SINDI_F32 ? 4 : 2;
+    if (tile_doc) HIP_TRY(hipMemcpy(tile_doc, ix->tile_doc.p, (size_t)(ix->n_tiles + 1) * 8, hipMemcpyDeviceToHost));
+    if (tile_post) HIP_TRY(hipMemcpy(tile_post, ix->tile_post.p, (size_t)(ix->n_tiles + 1) * 8, hipMemcpyDeviceToHost));
+    if (term_off) HIP_TRY(hipMemcpy(term_off, ix->term_off.p, (size_t)ix->n_tiles * (ix->n_cols + 1) * 4, hipMemcpyDeviceToHost));
+    if (post_doc && ix->n_post) HIP_TRY(hipMemcpy(post_doc, ix->post_doc.p, (size_t)ix->n_post * 2, hipMemcpyDeviceToHost));
+    if (post_val && ix->n_post) HIP_TRY(hipMemcpy(post_val, ix->post_val.p, (size_t)ix->n_post * vb, hipMemcpyDeviceToHost));
+    return SINDI_OK;
+}
+
+sindi_status sindi_search(const sindi_index *idx, const sindi_csr *queries, int32_t k,
+                          const sindi_search_params *params, int64_t *out_ids, float *out_scores,
+                          void *stream)
+{
+    try {
+        return search_impl(const_cast<sindi_index *>(idx), queries, k, params, out_ids, out_scores,
+                           (hipStream_t)stream, true, "sindi_search");
+    } catch (const std::bad_alloc &) {
+        return fail(SINDI_E_OOM, "sindi_search: host allocation failed");
+    } catch (...) {
+        return fail(SINDI_E_INTERNAL, "sindi_search: unexpected exception");
+    }
+}
+
+sindi_status sindi_search_coarse(const sindi_index *idx, const sindi_csr *queries, int32_t k,
+                                 const sindi_search_params *params, int64_t *out_ids,
+                                 float *out_scores, void *stream)
+{
+    try {
+        return search_impl(const_cast<sindi_index *>(idx), queries, k, params, out_ids, out_scores,
+                           (hipStream_t)stream, false, "sindi_search_coarse");
+    } catch (const std::bad_alloc &) {
+        return fail(SINDI_E_OOM, "sindi_search_coarse: host allocation failed");
+    } catch (...) {
+        return fail(SINDI_E_INTERNAL, "sindi_search_coarse: unexpected exception");
+    }
+}
+
+sindi_status sindi_score_forward(const sindi_index *idx, const sindi_csr *queries,
+                                 const int64_t *cand_ids, int32_t n_cand, float *out_scores,
+                                 void *stream)
+{
+    if (!idx || !queries || (!cand_ids && n_cand) || (!out_scores && n_cand) || n_cand < 0)
+        return fail(SINDI_E_INVALID, "sindi_score_forward: bad argument");
+    sindi_index *ix = const_cast<sindi_index *>(idx);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    sindi_status st = check_dev_queries(ix, queries, "sindi_score_forward", s);
+    if (st != SINDI_OK) return st;
+    DevQueries dq{queries->n_rows, queries->nnz, queries->indptr, queries->indices, queries->values};
+    HIP_TRY(launch_score_forward(ix->dev(), dq, cand_ids, n_cand, out_scores, s));
+    return SINDI_OK;
+}
+
+sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queries,
+                                  const int64_t *cand_ids, int32_t n_cand,
+                                  const float *grad_scores, float *grad_query_values,
+                                  float *grad_doc_values, void *stream)
+{
+    if (!idx || !queries || (!cand_ids && n_cand) || (!grad_scores && n_cand) || n_cand < 0)
+        return fail(SINDI_E_INVALID, "sindi_score_backward: bad argument");
+    sindi_index *ix = const_cast<sindi_index *>(idx);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    sindi_status st = check_dev_queries(ix, queries, "sindi_score_backward", s);
+    if (st != SINDI_OK) return st;
+    DevQueries dq{queries->n_rows, queries->nnz, queries->indptr, queries->indices, queries->values};
+    HIP_TRY(launch_score_backward(ix->dev(), dq, cand_ids, n_cand, grad_scores, grad_query_values,
+                                  grad_doc_values, s));
+    return SINDI_OK;
+}
+
+sindi_status sindi_profile_enable(int32_t enable)
+{
+    g_prof.on.store(enable != 0);
+    return SINDI_OK;
+}
+
+sindi_status sindi_profile_read(sindi_profile *out, int32_t reset)
+{
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    sindi_status st = SINDI_OK;
+    for (auto &r : g_prof.pending) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && st == SINDI_OK)
+            st = fail(SINDI_E_HIP, "sindi_profile_read: %s", hipGetErrorString(e));
+        g_prof.n[r.cat] += 1;
+        g_prof.ms[r.cat] += ms;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.pending.clear();
+    if (out)
+        for (int i = 0; i < 5; ++i) {
+            out->launches[i] = g_prof.n[i];
+            out->ms[i] = g_prof.ms[i];
+        }
+    if (reset)
+        for (int i = 0; i < 5; ++i) {
+            g_prof.n[i] = 0;
+            g_prof.ms[i] = 0.0;
+        }
+    return st;
+}
+
+const char *sindi_last_error(void) { return g_err.c_str(); }
+
+const char *sindi_version(void) { return "sindi-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

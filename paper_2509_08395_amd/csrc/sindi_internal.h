@@ -1,0 +1,83 @@
+// Internal declarations shared by the host side and the gfx950 kernels of the
+// SINDI library.  Not part of the C ABI (include/sindi.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sindi {
+
+// Device view of a built index: the value-storing lists of Alg. 1 cut into
+// score tiles (each window of Sec. 3.3.1 split into equal tiles), plus the
+// unpruned corpus kept for the exact rerank of Alg. 4.
+struct DevIndex {
+    int64_t n_docs, n_cols, n_tiles;
+    int32_t tile_stride;           // floats per query row of the on-chip score tile (>= tile_max, %4 == 0)
+    int32_t value_dtype;           // sindi_dtype
+    const int64_t *tile_doc;       // [n_tiles + 1] first document of each tile
+    const int64_t *tile_post;      // [n_tiles + 1] first posting of each tile
+    const uint32_t *term_off;      // [n_tiles * (n_cols + 1)] list starts relative to tile_post[t]
+    const uint16_t *post_doc;      // [n_postings + pad] document id - tile_doc[t]
+    const void *post_val;          // [n_postings + pad] value (f32 / f16 / bf16 bits)
+    const int64_t *indptr;         // unpruned corpus CSR, [n_docs + 1]
+    const int32_t *indices;        // [nnz]
+    const float *values;           // [nnz]
+    int64_t nnz;
+};
+
+// Queries as the device kernels see them.
+struct DevQueries {
+    int64_t n_rows, nnz;
+    const int64_t *indptr;
+    const int32_t *indices;
+    const float *values;
+};
+
+// Per-query coarse terms (beta-mass subvector, ascending term id), stored at
+// the query row's own positions: terms ct[indptr[q] + i], weights cw[...],
+// i < cn[q].
+struct DevCoarse {
+    int32_t *ct;
+    float *cw;
+    int32_t *cn;
+};
+
+constexpr int kAccThreads = 512;       // accumulate kernel workgroup
+constexpr int kFinThreads = 256;       // finalize / theta kernels
+constexpr int kGammaMax = 4096;        // largest reorder pool
+constexpr int kQueryHash = 8192;       // rerank hash slots (query nnz <= kQueryHash / 2)
+constexpr int kEntryBlock = 512;       // (query, term) entries staged per pass in the accumulate kernel
+constexpr int kChunkGroups = 128;      // 4-posting groups per work chunk (2 per lane)
+
+// Status codes written per query slot by the finalize kernel.
+enum SlotStatus : int32_t { kSlotOk = 0, kSlotRetry = 1 };
+
+// Kernel launchers (sindi_kernels.hip).  All return hipGetLastError().
+hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, DevCoarse c,
+                             double *scratch_abs, int32_t *err_flag, hipStream_t s);
+
+hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
+                             int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
+                             int32_t n_sample_tiles, float *maxima, const float *theta,
+                             uint32_t *count, uint64_t *cand, int64_t cap, hipStream_t s);
+
+hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,
+                        float *theta, hipStream_t s);
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+
+hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
+                           int32_t n_slots, const uint32_t *count, const uint64_t *cand,
+                           int64_t cap, int32_t need, int32_t k, bool rerank, int64_t *out_ids,
+                           float *out_scores, int32_t *status, hipStream_t s);
+
+hipError_t launch_score_forward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
+                                int32_t n_cand, float *out, hipStream_t s);
+
+hipError_t launch_score_backward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
+                                 int32_t n_cand, const float *grad, float *gq, float *gx,
+                                 hipStream_t s);
+
+}  // namespace sindi

@@ -1,0 +1,832 @@
+// gfx950 kernels of the SINDI search path (arXiv 2509.08395).
+//
+//   k_query_prep   validate query rows; beta-mass subvector (Def. 6, Sec. 4.1)
+//   k_accumulate   stream each query term's window list I_{j,w} (Alg. 2,
+//                  product + accumulate steps) into on-chip score tiles;
+//                  then either sample per-thread maxima (threshold pass) or
+//                  emit every tile score at or above the query's threshold
+//   k_theta        per-query candidate threshold from the sampled maxima
+//   k_finalize     exact top-gamma of the emitted candidates (Alg. 2 heap
+//                  update), exact FP32 rerank from the unpruned vectors and
+//                  top-k (Alg. 4), or coarse top-k only (Alg. 2)
+//   k_score_*      delta(q, x) of listed pairs (Def. 2) and its gradient
+//
+// Ranking order: score descending, then document id ascending.  A candidate
+// is one 64-bit key: (order-preserving score bits << 32) | (~doc id), so the
+// ranking order is plain descending key order and keys are unique.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "sindi_internal.h"
+
+namespace sindi {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint32_t ord_f32(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if (f == 0.0f) u = 0u;  // -0 ranks as +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(uint32_t o)
+{
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+__device__ __forceinline__ uint64_t make_key(float s, uint32_t doc)
+{
+    return ((uint64_t)ord_f32(s) << 32) | (uint64_t)(0xFFFFFFFFu - doc);
+}
+__device__ __forceinline__ uint32_t key_doc(uint64_t k) { return 0xFFFFFFFFu - (uint32_t)k; }
+__device__ __forceinline__ float key_score(uint64_t k) { return unord_f32((uint32_t)(k >> 32)); }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ void lds_add(float *p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t id, int lg)
+{
+    return ((uint32_t)id * 0x9E3779B1u) >> (32 - lg);
+}
+
+// Exclusive scan of one value per thread over the block; `total` = sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t &total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wsum[wave] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / kWave; ++i) {
+        uint32_t s = wsum[i];
+        off += (i < wave) ? s : 0u;
+        tot += s;
+    }
+    total = tot;
+    __syncthreads();
+    return off + x - v;
+}
+
+// r-th largest (1-based) of n keys, by most-significant-digit radix select:
+// one 256-bin histogram per byte of the key, restricted to the keys that
+// share the digits chosen so far.  Requires 1 <= r <= n.
+template <typename K, typename Load>
+__device__ K block_select(int64_t n, int64_t r, Load load, uint32_t *hist, int *s_digit,
+                          int64_t *s_need)
+{
+    K prefix = 0, mask = 0;
+    int64_t need = r;
+    for (int shift = (int)sizeof(K) * 8 - 8; shift >= 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            K key = load(i);
+            if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t acc = 0;
+            int d = 255;
+            for (; d > 0; --d) {
+                if (acc + (int64_t)hist[d] >= need) break;
+                acc += hist[d];
+            }
+            *s_digit = d;
+            *s_need = need - acc;
+        }
+        __syncthreads();
+        prefix |= (K)(*s_digit) << shift;
+        mask |= (K)0xFF << shift;
+        need = *s_need;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+// ------------------------------------------------------------------ queries
+// One wave per query row.  Flags malformed rows (err bits: 1 row pointers,
+// 2 term id out of range, 4 ids not strictly ascending, 8 non-finite value,
+// 16 more than kQueryHash / 2 entries)
+// and writes the coarse terms: the non-zero entries, cut to the beta-mass
+// subvector when beta < 1 (entries ranked by |q| descending, ties by id;
+// FP64 prefix sums in that order, the first prefix reaching beta * mass).
+__global__ __launch_bounds__(256) void k_query_prep(DevQueries q, int64_t n_cols, double beta,
+                                                    DevCoarse c, double *sabs, int32_t *err)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x / kWave);
+    if (row >= q.n_rows) return;
+    int64_t a = q.indptr[row], b = q.indptr[row + 1];
+    int bad = 0;
+    if (a < 0 || b < a || b > q.nnz || (row == 0 && a != 0) || (row == q.n_rows - 1 && b != q.nnz))
+        bad |= 1;
+    a = a < 0 ? 0 : (a > q.nnz ? q.nnz : a);
+    b = b < a ? a : (b > q.nnz ? q.nnz : b);
+    if (b - a > kQueryHash / 2) bad |= 16;
+    for (int64_t e = a + lane; e < b; e += kWave) {
+        int32_t id = q.indices[e];
+        float v = q.values[e];
+        if (id < 0 || id >= n_cols) bad |= 2;
+        if (e + 1 < b && q.indices[e + 1] <= id) bad |= 4;
+        if (!isfinite(v)) bad |= 8;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) bad |= __shfl_xor(bad, m, kWave);
+    if (bad) {
+        if (lane == 0) {
+            atomicOr(err, bad);
+            c.cn[row] = 0;
+        }
+        return;
+    }
+    int32_t r_keep = 0x7FFFFFFF;  // rank bound of kept entries
+    if (beta < 1.0) {
+        // rank of every non-zero entry in pi order; |x| placed at its rank
+        int32_t nz = 0;
+        for (int64_t e0 = a; e0 < b; e0 += kWave) {
+            bool p = (e0 + lane < b) && q.values[e0 + lane] != 0.0f;
+            nz += __popcll(__ballot(p));
+        }
+        for (int64_t e = a + lane; e < b; e += kWave) {
+            float v = q.values[e];
+            if (v == 0.0f) continue;
+            float av = fabsf(v);
+            int32_t id = q.indices[e];
+            int32_t rank = 0;
+            for (int64_t f = a; f < b; ++f) {
+                float w = fabsf(q.values[f]);
+                if (w == 0.0f) continue;
+                int32_t jd = q.indices[f];
+                rank += (w > av || (w == av && jd < id)) ? 1 : 0;
+            }
+            sabs[a + rank] = (double)av;
+        }
+        __threadfence();
+        int32_t r = 0;
+        if (lane == 0) {
+            double mass = 0.0;
+            for (int32_t t = 0; t < nz; ++t) mass += sabs[a + t];
+            double thr = beta * mass;
+            double run = 0.0;
+            while (r < nz) {
+                run += sabs[a + r];
+                ++r;
+                if (run >= thr) break;
+            }
+        }
+        r_keep = __shfl(r, 0, kWave);
+    }
+    // ordered compaction of the kept entries (ascending term id preserved)
+    int32_t base = 0;
+    for (int64_t e0 = a; e0 < b; e0 += kWave) {
+        int64_t e = e0 + lane;
+        bool keep = false;
+        float v = 0.0f;
+        int32_t id = 0;
+        if (e < b) {
+            v = q.values[e];
+            id = q.indices[e];
+            keep = v != 0.0f;
+            if (keep && r_keep != 0x7FFFFFFF) {
+                float av = fabsf(v);
+                int32_t rank = 0;
+                for (int64_t f = a; f < b; ++f) {
+                    float w = fabsf(q.values[f]);
+                    if (w == 0.0f) continue;
+                    int32_t jd = q.indices[f];
+                    rank += (w > av || (w == av && jd < id)) ? 1 : 0;
+                }
+                keep = rank < r_keep;
+            }
+        }
+        uint64_t m = __ballot(keep);
+        if (keep) {
+            int32_t p = base + (int32_t)lanes_below(m);
+            c.ct[a + p] = id;
+            c.cw[a + p] = v;
+        }
+        base += __popcll(m);
+    }
+    if (lane == 0) c.cn[row] = base;
+}
+
+// ------------------------------------------------------------------ accumulate
+template <int VT> struct Val;
+template <> struct Val<0> {  // FP32
+    static __device__ __forceinline__ void load(const void *p, uint64_t g, float (&v)[4])
+    {
+        uint4 r = reinterpret_cast<const uint4 *>(p)[g];
+        v[0] = __uint_as_float(r.x);
+        v[1] = __uint_as_float(r.y);
+        v[2] = __uint_as_float(r.z);
+        v[3] = __uint_as_float(r.w);
+    }
+};
+template <> struct Val<1> {  // FP16
+    static __device__ __forceinline__ float h2f(uint32_t h)
+    {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+    }
+    static __device__ __forceinline__ void load(const void *p, uint64_t g, float (&v)[4])
+    {
+        uint2 r = reinterpret_cast<const uint2 *>(p)[g];
+        v[0] = h2f(r.x & 0xFFFFu);
+        v[1] = h2f(r.x >> 16);
+        v[2] = h2f(r.y & 0xFFFFu);
+        v[3] = h2f(r.y >> 16);
+    }
+};
+template <> struct Val<2> {  // BF16
+    static __device__ __forceinline__ void load(const void *p, uint64_t g, float (&v)[4])
+    {
+        uint2 r = reinterpret_cast<const uint2 *>(p)[g];
+        v[0] = __uint_as_float(r.x << 16);
+        v[1] = __uint_as_float(r.x & 0xFFFF0000u);
+        v[2] = __uint_as_float(r.y << 16);
+        v[3] = __uint_as_float(r.y & 0xFFFF0000u);
+    }
+};
+
+// One workgroup = one tile of documents x a batch of B query slots.  The
+// tile's score rows A[b][0..len) live in LDS (the window's distance array of
+// Sec. 3.3.1, one row per query).  Work list: for every (query, term) entry,
+// the list I_{term, tile} cut into chunks of kChunkGroups aligned 4-posting
+// groups; waves take chunks round-robin.  Every posting adds
+// q_b^term * x to A[b][doc] (product, then add, as Alg. 2 stores P^j then
+// accumulates).  Different terms may hit one document concurrently, so the
+// adds are LDS atomics.
+template <int VT, int B, bool SAMPLE>
+__global__ __launch_bounds__(kAccThreads) void k_accumulate(
+    DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
+    int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
+    int64_t cap)
+{
+    constexpr int NT = kAccThreads, NW = NT / kWave;
+    static_assert(kEntryBlock == NT, "one staged entry per thread");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int T = ix.tile_stride;
+    float *A = reinterpret_cast<float *>(smem);
+    uint32_t *e_lo = reinterpret_cast<uint32_t *>(A + (size_t)B * T);
+    uint32_t *e_hi = e_lo + kEntryBlock;
+    float *e_w = reinterpret_cast<float *>(e_hi + kEntryBlock);
+    uint32_t *e_b = reinterpret_cast<uint32_t *>(e_w + kEntryBlock);
+    uint32_t *cpre = e_b + kEntryBlock;  // kEntryBlock + 1
+    __shared__ int64_t s_qa[B];
+    __shared__ int32_t s_qpre[B + 1];
+    __shared__ int32_t s_slot[B];
+    __shared__ uint32_t s_wsum[NW];
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int32_t batch = blockIdx.x;
+
+    if (tid == 0) {
+        int32_t acc = 0;
+        for (int b = 0; b < B; ++b) {
+            int32_t s = batch * B + b;
+            int32_t n = 0;
+            int64_t qa = 0;
+            if (s < n_slots) {
+                int32_t row = slot_q ? slot_q[s] : s;
+                qa = q.indptr[row];
+                n = c.cn[row];
+            }
+            s_slot[b] = s < n_slots ? s : -1;
+            s_qa[b] = qa;
+            s_qpre[b] = acc;
+            acc += n;
+        }
+        s_qpre[B] = acc;
+    }
+    __syncthreads();
+    const int32_t n_e = s_qpre[B];
+    const int64_t n_tile_iter = SAMPLE ? n_sample : ix.n_tiles;
+
+    for (int64_t ti = blockIdx.y; ti < n_tile_iter; ti += gridDim.y) {
+        const int64_t t = SAMPLE ? (ti * ix.n_tiles / n_sample) : ti;
+        const int64_t d0 = ix.tile_doc[t];
+        const int32_t len = (int32_t)(ix.tile_doc[t + 1] - d0);
+        const uint64_t P0 = (uint64_t)ix.tile_post[t];
+        const uint32_t *toff = ix.term_off + (size_t)t * (size_t)(ix.n_cols + 1);
+
+        float4 *A4 = reinterpret_cast<float4 *>(A);
+        for (int i = tid; i < B * T / 4; i += NT) A4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+
+        for (int32_t eb = 0; eb < n_e; eb += kEntryBlock) {
+            const int32_t ne = min(kEntryBlock, n_e - eb);
+            uint32_t nch = 0;
+            if (tid < ne) {
+                const int32_t e = eb + tid;
+                int b = 0;
+                while (b + 1 < B && s_qpre[b + 1] <= e) ++b;
+                const int64_t pos = s_qa[b] + (e - s_qpre[b]);
+                const int32_t term = c.ct[pos];
+                const uint32_t lo = toff[term], hi = toff[term + 1];
+                e_lo[tid] = lo;
+                e_hi[tid] = hi;
+                e_w[tid] = c.cw[pos];
+                e_b[tid] = (uint32_t)b;
+                if (hi > lo) {
+                    const uint64_t g0 = (P0 + lo) >> 2, g1 = (P0 + hi + 3) >> 2;
+                    nch = (uint32_t)((g1 - g0 + kChunkGroups - 1) / kChunkGroups);
+                }
+            }
+            uint32_t total;
+            const uint32_t ex = block_excl_scan<NT>(nch, s_wsum, total);
+            cpre[tid] = ex;
+            if (tid == 0) cpre[ne] = total;
+            __syncthreads();
+
+            for (uint32_t ch = wave; ch < total; ch += NW) {
+                int lo_ = 0, hi_ = ne - 1;
+                while (lo_ < hi_) {
+                    const int mid = (lo_ + hi_ + 1) >> 1;
+                    if (cpre[mid] <= ch) lo_ = mid; else hi_ = mid - 1;
+                }
+                const int u = lo_;
+                const uint64_t plo = P0 + e_lo[u], phi = P0 + e_hi[u];
+                const uint64_t gbeg = (plo >> 2) + (uint64_t)(ch - cpre[u]) * kChunkGroups;
+                const uint64_t glim = (phi + 3) >> 2;
+                const uint64_t gend = glim < gbeg + kChunkGroups ? glim : gbeg + kChunkGroups;
+                const float w = e_w[u];
+                float *Ab = A + (size_t)e_b[u] * T;
+                constexpr int G = kChunkGroups / kWave;
+                uint2 ids[G];
+                float v[G][4];
+#pragma unroll
+                for (int i = 0; i < G; ++i) {
+                    const uint64_t g = gbeg + (uint64_t)(i * kWave + lane);
+                    if (g < gend) {
+                        ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g];
+                        Val<VT>::load(ix.post_val, g, v[i]);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < G; ++i) {
+                    const uint64_t g = gbeg + (uint64_t)(i * kWave + lane);
+                    if (g < gend) {
+                        const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16,
+                                                ids[i].y & 0xFFFFu, ids[i].y >> 16};
+#pragma unroll
+                        for (int p = 0; p < 4; ++p) {
+                            const uint64_t pos = 4 * g + p;
+                            if (pos >= plo && pos < phi) lds_add(&Ab[d4[p]], w * v[i][p]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        for (int b = 0; b < B; ++b) {
+            const int32_t slot = s_slot[b];
+            if (slot < 0) continue;
+            const float *Ar = A + (size_t)b * T;
+            if (SAMPLE) {
+                float mx = -INFINITY;
+                for (int m = tid; m < len; m += NT) mx = fmaxf(mx, Ar[m]);
+                maxima[((size_t)slot * n_sample + ti) * NT + tid] = mx;
+            } else {
+                const float th = theta[slot];
+                uint32_t *cnt = count + slot;
+                uint64_t *out = cand + (size_t)slot * (size_t)cap;
+                for (int base = wave * 256; base < len; base += NW * 256) {
+                    const int m0 = base + lane * 4;
+                    float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (m0 < len) s4 = *reinterpret_cast<const float4 *>(Ar + m0);
+                    const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+                    bool pr[4];
+                    uint64_t bal[4];
+                    uint32_t tot = 0;
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        pr[p] = (m0 + p < len) && sv[p] >= th;
+                        bal[p] = __ballot(pr[p]);
+                        tot += (uint32_t)__popcll(bal[p]);
+                    }
+                    if (tot == 0) continue;
+                    uint32_t b0 = 0;
+                    if (lane == 0) b0 = atomicAdd(cnt, tot);
+                    b0 = __shfl(b0, 0, kWave);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        if (pr[p]) {
+                            const uint64_t pos = (uint64_t)b0 + lanes_below(bal[p]);
+                            if (pos < (uint64_t)cap)
+                                out[pos] = make_key(sv[p], (uint32_t)(d0 + m0 + p));
+                        }
+                        b0 += (uint32_t)__popcll(bal[p]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ threshold
+// theta = the rank-th largest sampled maximum, lowered by 2^-12 of its
+// magnitude so that FP32 summation-order differences between the sampling
+// and the scoring pass cannot lift a document out of the kept set.  The
+// finalize kernel verifies the result (at least gamma candidates kept).
+__global__ __launch_bounds__(kFinThreads) void k_theta(const float *maxima, int64_t n_m,
+                                                       int64_t rank, float *theta)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ int s_digit;
+    __shared__ int64_t s_need;
+    const float *mx = maxima + (size_t)blockIdx.x * (size_t)n_m;
+    const uint32_t key = block_select<uint32_t>(
+        n_m, rank, [&](int64_t i) { return ord_f32(mx[i]); }, hist, &s_digit, &s_need);
+    if (threadIdx.x == 0) {
+        float th = unord_f32(key);
+        if (!(th > -INFINITY)) th = -INFINITY;
+        else th = th - fabsf(th) * (1.0f / 4096.0f);
+        theta[blockIdx.x] = th;
+    }
+}
+
+__global__ void k_fill_f32(float *p, int64_t n, float v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------ finalize
+struct QueryHash {
+    int32_t *id;
+    float *val;
+    int32_t *pos;
+    int lg;
+};
+
+// Full (unpruned) query row into an open-addressing LDS table.
+__device__ void build_query_hash(const DevQueries &q, int64_t a, int64_t b, QueryHash h)
+{
+    const int H = 1 << h.lg;
+    for (int i = threadIdx.x; i < H; i += blockDim.x) h.id[i] = -1;
+    __syncthreads();
+    for (int64_t e = a + threadIdx.x; e < b; e += blockDim.x) {
+        const int32_t id = q.indices[e];
+        uint32_t s = hash_slot(id, h.lg);
+        while (atomicCAS(&h.id[s], -1, id) != -1) s = (s + 1) & (uint32_t)(H - 1);
+        h.val[s] = q.values[e];
+        if (h.pos) h.pos[s] = (int32_t)(e - a);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int probe(const QueryHash &h, int32_t id)
+{
+    const uint32_t mask = (1u << h.lg) - 1u;
+    uint32_t s = hash_slot(id, h.lg);
+    for (;;) {
+        const int32_t k = h.id[s];
+        if (k == id) return (int)s;
+        if (k == -1) return -1;
+        s = (s + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ int hash_lg(int64_t n)
+{
+    int lg = 6;
+    while ((1ll << lg) < 2 * n) ++lg;
+    return lg;
+}
+
+// delta(q, x_doc) in FP32 by one wave over the document's row.
+__device__ __forceinline__ float wave_dot(const DevIndex &ix, const QueryHash &h, uint32_t doc)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t ra = ix.indptr[doc], rb = ix.indptr[doc + 1];
+    float acc = 0.0f;
+    for (int64_t e = ra + lane; e < rb; e += kWave) {
+        const int s = probe(h, ix.indices[e]);
+        if (s >= 0) acc = fmaf(h.val[s], ix.values[e], acc);
+    }
+    return wave_sum(acc);
+}
+
+template <bool RERANK>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(
+    DevIndex ix, DevQueries q, const int32_t *slot_q, const uint32_t *count, const uint64_t *cand,
+    int64_t cap, int32_t need, int32_t k, int64_t *out_ids, float *out_scores, int32_t *status)
+{
+    constexpr int NT = kFinThreads, NW = NT / kWave;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t *keys = reinterpret_cast<uint64_t *>(smem);                   // [kGammaMax]
+    int32_t *hid = reinterpret_cast<int32_t *>(keys + kGammaMax);           // [kQueryHash]
+    float *hval = reinterpret_cast<float *>(hid + kQueryHash);              // [kQueryHash]
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_n;
+    __shared__ int s_digit;
+    __shared__ int64_t s_need;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int32_t slot = blockIdx.x;
+    const int32_t row = slot_q ? slot_q[slot] : slot;
+    const uint32_t cnt = count[slot];
+    if ((int64_t)cnt > cap || (int64_t)cnt < (int64_t)need) {
+        if (tid == 0) status[row] = kSlotRetry;
+        return;
+    }
+    const uint64_t *cs = cand + (size_t)slot * (size_t)cap;
+    const uint64_t kth = block_select<uint64_t>(
+        cnt, need, [&](int64_t i) { return cs[i]; }, hist, &s_digit, &s_need);
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < cnt; i += NT) {
+        const uint64_t key = cs[i];
+        if (key >= kth) {
+            const uint32_t p = atomicAdd(&s_n, 1u);
+            if (p < (uint32_t)kGammaMax) keys[p] = key;
+        }
+    }
+    __syncthreads();
+
+    if (RERANK) {
+        const int64_t qa = q.indptr[row], qb = q.indptr[row + 1];
+        const QueryHash h{hid, hval, nullptr, hash_lg(qb - qa)};
+        build_query_hash(q, qa, qb, h);
+        for (int ci = wave; ci < need; ci += NW) {
+            const uint64_t key = keys[ci];
+            const float s = wave_dot(ix, h, key_doc(key));
+            if (lane == 0) keys[ci] = ((uint64_t)ord_f32(s) << 32) | (key & 0xFFFFFFFFull);
+        }
+        __syncthreads();
+    }
+
+    int P = 1;
+    while (P < need) P <<= 1;
+    for (int i = need + tid; i < P; i += NT) keys[i] = 0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += NT) {
+                const int ij = i ^ j;
+                if (ij > i) {
+                    const uint64_t x = keys[i], y = keys[ij];
+                    const bool desc = (i & kk) == 0;
+                    if (desc ? (x < y) : (x > y)) {
+                        keys[i] = y;
+                        keys[ij] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = tid; r < k; r += NT) {
+        const size_t o = (size_t)row * (size_t)k + r;
+        if (r < need) {
+            out_ids[o] = (int64_t)key_doc(keys[r]);
+            out_scores[o] = key_score(keys[r]);
+        } else {
+            out_ids[o] = -1;
+            out_scores[o] = -INFINITY;
+        }
+    }
+    if (tid == 0) status[row] = kSlotOk;
+}
+
+// ------------------------------------------------------------------ pair scores
+__global__ __launch_bounds__(kFinThreads) void k_score_forward(DevIndex ix, DevQueries q,
+                                                               const int64_t *cand,
+                                                               int32_t n_cand, float *out)
+{
+    constexpr int NW = kFinThreads / kWave;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *hid = reinterpret_cast<int32_t *>(smem);
+    float *hval = reinterpret_cast<float *>(hid + kQueryHash);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t b = blockIdx.x;
+    const int64_t qa = q.indptr[b], qb = q.indptr[b + 1];
+    const QueryHash h{hid, hval, nullptr, hash_lg(qb - qa)};
+    build_query_hash(q, qa, qb, h);
+    for (int c = wave; c < n_cand; c += NW) {
+        const int64_t d = cand[b * n_cand + c];
+        float s = 0.0f;
+        if (d >= 0 && d < ix.n_docs) s = wave_dot(ix, h, (uint32_t)d);
+        if (lane == 0) out[b * n_cand + c] = s;
+    }
+}
+
+// Gradients of s[b][c] = delta(q_b, x_c): every common dimension t adds
+// G[b][c] * x_c[t] to the query entry and G[b][c] * q_b[t] to the document
+// entry.  Query-side sums stay in LDS (one workgroup per query); document
+// entries can be shared by several queries, so they take global atomics.
+__global__ __launch_bounds__(kFinThreads) void k_score_backward(
+    DevIndex ix, DevQueries q, const int64_t *cand, int32_t n_cand, const float *grad, float *gq,
+    float *gx)
+{
+    constexpr int NW = kFinThreads / kWave;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *hid = reinterpret_cast<int32_t *>(smem);
+    float *hval = reinterpret_cast<float *>(hid + kQueryHash);
+    int32_t *hpos = reinterpret_cast<int32_t *>(hval + kQueryHash);
+    float *gacc = reinterpret_cast<float *>(hpos + kQueryHash);
+    uint32_t *gtouch = reinterpret_cast<uint32_t *>(gacc + kQueryHash / 2);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t b = blockIdx.x;
+    const int64_t qa = q.indptr[b], qb = q.indptr[b + 1];
+    const int n = (int)(qb - qa);
+    const QueryHash h{hid, hval, hpos, hash_lg(n)};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        gacc[i] = 0.0f;
+        gtouch[i] = 0u;
+    }
+    build_query_hash(q, qa, qb, h);
+    for (int c = wave; c < n_cand; c += NW) {
+        const int64_t d = cand[b * n_cand + c];
+        if (d < 0 || d >= ix.n_docs) continue;
+        const float g = grad[b * n_cand + c];
+        const int64_t ra = ix.indptr[d], rb = ix.indptr[d + 1];
+        for (int64_t e = ra + lane; e < rb; e += kWave) {
+            const int s = probe(h, ix.indices[e]);
+            if (s < 0) continue;
+            if (gq) {
+                lds_add(&gacc[hpos[s]], g * ix.values[e]);
+                gtouch[hpos[s]] = 1u;
+            }
+            if (gx) atomicAdd(&gx[e], g * hval[s]);
+        }
+    }
+    __syncthreads();
+    if (gq)
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            if (gtouch[i]) gq[qa + i] += gacc[i];
+}
+
+template <typename F>
+hipError_t set_lds(F *kernel, size_t bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int VT, int B, bool SAMPLE>
+hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
+                          const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
+                          const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
+                          hipStream_t s)
+{
+    const size_t lds = (size_t)B * ix.tile_stride * sizeof(float) +
+                       (size_t)(5 * kEntryBlock + 1) * sizeof(uint32_t);
+    hipError_t e = set_lds(k_accumulate<VT, B, SAMPLE>, lds);
+    if (e != hipSuccess) return e;
+    const int64_t n_batches = (n_slots + B - 1) / B;
+    const int64_t ny = SAMPLE ? n_sample : ix.n_tiles;
+    dim3 grid((unsigned)n_batches, (unsigned)(ny < 65535 ? ny : 65535));
+    hipLaunchKernelGGL((k_accumulate<VT, B, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
+                       slot_q, n_slots, n_sample, maxima, theta, count, cand, cap);
+    return hipGetLastError();
+}
+
+template <int VT, bool SAMPLE>
+hipError_t dispatch_b(int batch, const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
+                      const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
+                      const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
+                      hipStream_t s)
+{
+    switch (batch) {
+    case 1: return run_accumulate<VT, 1, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
+    case 2: return run_accumulate<VT, 2, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
+    case 4: return run_accumulate<VT, 4, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
+    case 8: return run_accumulate<VT, 8, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, DevCoarse c,
+                             double *scratch_abs, int32_t *err_flag, hipStream_t s)
+{
+    if (q.n_rows == 0) return hipSuccess;
+    dim3 grid((unsigned)((q.n_rows + 3) / 4));
+    hipLaunchKernelGGL(k_query_prep, grid, dim3(256), 0, s, q, n_cols, beta, c, scratch_abs,
+                       err_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
+                             int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
+                             int32_t n_sample_tiles, float *maxima, const float *theta,
+                             uint32_t *count, uint64_t *cand, int64_t cap, hipStream_t s)
+{
+    if (n_slots == 0 || ix.n_tiles == 0) return hipSuccess;
+    const int vt = ix.value_dtype;
+    if (sample) {
+        if (vt == 0) return dispatch_b<0, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+        if (vt == 1) return dispatch_b<1, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+        return dispatch_b<2, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+    }
+    if (vt == 0) return dispatch_b<0, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+    if (vt == 1) return dispatch_b<1, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+    return dispatch_b<2, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+}
+
+hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,
+                        float *theta, hipStream_t s)
+{
+    if (n_slots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_theta, dim3((unsigned)n_slots), dim3(kFinThreads), 0, s, maxima,
+                       n_maxima, rank, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
+                           int32_t n_slots, const uint32_t *count, const uint64_t *cand,
+                           int64_t cap, int32_t need, int32_t k, bool rerank, int64_t *out_ids,
+                           float *out_scores, int32_t *status, hipStream_t s)
+{
+    if (n_slots == 0) return hipSuccess;
+    const size_t lds = (size_t)kGammaMax * 8 + (size_t)kQueryHash * 8;
+    hipError_t e;
+    if (rerank) {
+        e = set_lds(k_finalize<true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_finalize<true>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
+                           ix, q, slot_q, count, cand, cap, need, k, out_ids, out_scores, status);
+    } else {
+        e = set_lds(k_finalize<false>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_finalize<false>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
+                           ix, q, slot_q, count, cand, cap, need, k, out_ids, out_scores, status);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_score_forward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
+                                int32_t n_cand, float *out, hipStream_t s)
+{
+    if (q.n_rows == 0 || n_cand == 0) return hipSuccess;
+    const size_t lds = (size_t)kQueryHash * 8;
+    hipError_t e = set_lds(k_score_forward, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_score_forward, dim3((unsigned)q.n_rows), dim3(kFinThreads), lds, s, ix,
+                       q, cand, n_cand, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_score_backward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
+                                 int32_t n_cand, const float *grad, float *gq, float *gx,
+                                 hipStream_t s)
+{
+    if (q.n_rows == 0 || n_cand == 0) return hipSuccess;
+    const size_t lds = (size_t)kQueryHash * 12 + (size_t)(kQueryHash / 2) * 8;
+    hipError_t e = set_lds(k_score_backward, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_score_backward, dim3((unsigned)q.n_rows), dim3(kFinThreads), lds, s, ix,
+                       q, cand, n_cand, grad, gq, gx);
+    return hipGetLastError();
+}
+
+}  // namespace sindi

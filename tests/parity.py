@@ -1,0 +1,77 @@
+"""Comparison of GPU results with the oracle, tolerant only where several answers are right.
+
+Floating-point ranking has ties within rounding: when two documents' exact
+scores differ by less than the FP32 error bound, either may legitimately
+take the last place of a top-k (or of the rerank pool).  The comparisons
+below accept an id mismatch only when it is explained that way; everything
+else must match exactly.
+"""
+import numpy as np
+
+import oracle
+import synth
+
+
+def abs_csr(c):
+    return synth.Csr(c.indptr, c.indices, np.abs(c.values), c.n_cols)
+
+
+def score_scale(corpus, queries, qrows, docs):
+    """sum_t |q_t x_t| per pair: the scale of the FP32 rounding error of delta."""
+    return oracle.pair_scores(abs_csr(corpus), abs_csr(queries), qrows, docs)
+
+
+def check_scores(corpus, queries, ids, scores, rtol):
+    """Every returned id's score is delta(x_id, q) within rtol of its error scale."""
+    nq, k = ids.shape
+    qrows = np.repeat(np.arange(nq), k)
+    flat = ids.reshape(-1)
+    valid = flat >= 0
+    exact = oracle.pair_scores(corpus, queries, qrows[valid], flat[valid])
+    scale = score_scale(corpus, queries, qrows[valid], flat[valid])
+    got = scores.reshape(-1)[valid].astype(np.float64)
+    err = np.abs(got - exact)
+    bad = err > rtol * np.maximum(scale, 1e-30)
+    assert not bad.any(), (
+        f"{bad.sum()} scores off; worst rel {np.max(err / np.maximum(scale, 1e-30)):.3g}")
+    assert np.isneginf(scores.reshape(-1)[~valid]).all()
+    return exact
+
+
+def check_ranked(ids, scores):
+    """Rows are sorted by (score desc, id asc) with ids unique; padding (-1) at the end."""
+    for r in range(ids.shape[0]):
+        v = ids[r] >= 0
+        n = int(v.sum())
+        assert v[:n].all() and not v[n:].any()
+        assert len(set(ids[r, :n].tolist())) == n
+        s = scores[r, :n]
+        i = ids[r, :n]
+        assert all((s[t] > s[t + 1]) or (s[t] == s[t + 1] and i[t] < i[t + 1]) for t in range(n - 1))
+
+
+def check_same_topk(gpu_ids, ref_ids, ref_scores, tol_abs, pool_margin=None):
+    """gpu top-k == reference top-k except near-ties.
+
+    A reference id missing from the GPU row is accepted if its reference score is
+    within tol_abs[row] of the reference k-th score, or, for the approximate method,
+    if pool_margin(row, id) says its coarse score sat at the pool boundary.
+    """
+    for r in range(ref_ids.shape[0]):
+        ref = [int(x) for x in ref_ids[r] if x >= 0]
+        got = set(int(x) for x in gpu_ids[r] if x >= 0)
+        assert len(got) == len(ref), (r, len(got), len(ref))
+        kth = ref_scores[r][len(ref) - 1] if ref else 0.0
+        for pos, d in enumerate(ref):
+            if d in got:
+                continue
+            s = ref_scores[r][pos]
+            if abs(s - kth) <= tol_abs[r]:
+                continue
+            if pool_margin is not None and pool_margin(r, d):
+                continue
+            raise AssertionError(f"row {r}: id {d} (score {s}, kth {kth}) missing from GPU result")
+
+
+def recall(gpu_ids, truth_ids):
+    return oracle.recall_at_k(gpu_ids, truth_ids)

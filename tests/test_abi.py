@@ -1,0 +1,92 @@
+"""The C ABI library: loads, exports every declared symbol, validates on the host (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "sindi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sindi_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2509_08395_amd import _lib
+    lib = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+    assert b"gfx950" in lib.sindi_version()
+
+
+def test_no_cpu_fallback_in_package():
+    """The product path has no route to the oracle or to a CPU implementation."""
+    pkg = os.path.join(ROOT, "paper_2509_08395_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "liboracle" not in src, f
+
+
+def _csr_struct(indptr, indices, values, n_cols):
+    from paper_2509_08395_amd import _lib
+    indptr = np.ascontiguousarray(indptr, np.int64)
+    indices = np.ascontiguousarray(indices, np.int32)
+    values = np.ascontiguousarray(values, np.float32)
+    s = _lib.SindiCsr(indptr.shape[0] - 1, n_cols, int(indptr[-1]), indptr.ctypes.data,
+                      indices.ctypes.data, values.ctypes.data, 0, 0)
+    return s, (indptr, indices, values)
+
+
+@pytest.mark.parametrize("case,msg", [
+    (([0, 2], [3, 1], [1.0, 1.0]), "ascending"),
+    (([0, 2], [1, 1], [1.0, 1.0]), "ascending"),
+    (([0, 1], [10], [1.0]), "out of range"),
+    (([0, 1], [-1], [1.0]), "out of range"),
+    (([0, 1], [1], [np.nan]), "non-finite"),
+    (([0, 1], [1], [np.inf]), "non-finite"),
+    (([0, 2, 1], [1, 2], [1.0, 1.0]), "indptr"),
+])
+def test_build_rejects_malformed_corpus_before_any_device_work(case, msg):
+    from paper_2509_08395_amd import _lib
+    lib = _lib.load()
+    s, keep = _csr_struct(*case, n_cols=5)
+    p = _lib.SindiBuildParams(0.5, 10, 0, 0)
+    h = ctypes.c_void_p()
+    rc = lib.sindi_build(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == _lib.SINDI_E_INVALID
+    err = lib.sindi_last_error().decode()
+    assert msg in err or "indptr" in err or "monotone" in err, err
+    assert not h.value
+
+
+@pytest.mark.parametrize("alpha,window,dtype,tile", [
+    (0.0, 10, 0, 0), (1.5, 10, 0, 0), (0.5, 0, 0, 0), (0.5, 10, 7, 0), (0.5, 10, 0, 70000)])
+def test_build_rejects_bad_parameters(alpha, window, dtype, tile):
+    from paper_2509_08395_amd import _lib
+    lib = _lib.load()
+    s, keep = _csr_struct([0, 1], [1], [1.0], n_cols=5)
+    p = _lib.SindiBuildParams(alpha, window, dtype, tile)
+    h = ctypes.c_void_p()
+    assert lib.sindi_build(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(h)) == _lib.SINDI_E_INVALID
+
+
+def test_null_arguments_are_errors_not_crashes():
+    from paper_2509_08395_amd import _lib
+    lib = _lib.load()
+    assert lib.sindi_build(None, None, None, None) == _lib.SINDI_E_INVALID
+    assert lib.sindi_search(None, None, 10, None, None, None, None) == _lib.SINDI_E_INVALID
+    assert lib.sindi_index_get_info(None, None) == _lib.SINDI_E_INVALID
+    assert lib.sindi_score_forward(None, None, None, 0, None, None) == _lib.SINDI_E_INVALID
+    lib.sindi_index_free(None)

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by element."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import csr_from_dict_rows, load_golden
+from parity import check_ranked, check_same_topk, check_scores, score_scale
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sindi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_08395_amd as s
+    s._lib.load()
+    return s
+
+
+# A corpus spanning several windows and tiles, with ragged last window and tiles.
+N_DOCS, VOCAB, WINDOW, TILE = 30_011, 2_000, 7_000, 2_048
+
+
+@pytest.fixture(scope="module")
+def small():
+    corpus = synth.generate(N_DOCS, VOCAB, nnz=("poisson", 40.0), seed=11)
+    queries = synth.generate(64, VOCAB, nnz=("poisson", 12.0), seed=11, stream=1)
+    return corpus, queries
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _tol_kth(corpus, queries, ref_ids, ref_scores, rtol):
+    """Absolute near-tie tolerance at each row's last place."""
+    nq, k = ref_ids.shape
+    last = np.array([ref_ids[r][ref_ids[r] >= 0][-1] if (ref_ids[r] >= 0).any() else 0
+                     for r in range(nq)])
+    sc = score_scale(corpus, queries, np.arange(nq), last)
+    return 2.0 * rtol * np.maximum(sc, 1e-30)
+
+
+# ------------------------------------------------------------------ index layout
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_index_layout_is_alg1_bit_exact(sindi, small, dtype):
+    corpus, _ = small
+    alpha = 0.5
+    idx = sindi.Index(corpus, alpha=alpha, window=WINDOW, value_dtype=dtype, tile=TILE)
+    ex = idx.export()
+    info = idx.info()
+    keep = oracle.mass_prune(corpus, alpha)
+    ref = oracle.build_index(corpus, WINDOW, keep)
+    assert info["n_postings"] == int(keep.sum())
+    assert info["n_windows"] == ref.sigma
+    tile_doc, tile_post, term_off = ex["tile_doc"], ex["tile_post"], ex["term_off"]
+    assert tile_doc[0] == 0 and tile_doc[-1] == N_DOCS
+    assert (np.diff(tile_doc) <= TILE).all() and (np.diff(tile_doc) > 0).all()
+    # tiles never straddle a window boundary
+    assert ((tile_doc[:-1] // WINDOW) == ((tile_doc[1:] - 1) // WINDOW)).all()
+    nt = tile_doc.shape[0] - 1
+    tile_of = np.repeat(np.arange(nt), np.diff(tile_post))
+    term_of = np.concatenate([np.repeat(np.arange(VOCAB), np.diff(term_off[t])) for t in range(nt)])
+    doc = ex["post_doc"].astype(np.int64) + tile_doc[tile_of]
+    win = doc // WINDOW
+    order = np.lexsort((doc, win, term_of))  # Alg. 1 order: term, window, document
+    ref_docs = ref.doc.astype(np.int64)
+    ref_win = ref_docs // WINDOW
+    ref_term = np.repeat(np.arange(VOCAB), np.diff(ref.ptr[::ref.sigma]))
+    assert (doc[order] == ref_docs).all()
+    assert (win[order] == ref_win).all()
+    assert (term_of[order] == ref_term).all()
+    # inside every (tile, term) list the documents ascend
+    same = (tile_of[1:] == tile_of[:-1]) & (term_of[1:] == term_of[:-1])
+    assert (np.diff(doc)[same] > 0).all()
+    vals = ex["post_val"][order]
+    if dtype == "f32":
+        assert vals.view(np.uint32).tolist() == ref.val.view(np.uint32).tolist()
+    elif dtype == "f16":
+        assert vals.tolist() == ref.val.astype(np.float16).view(np.uint16).tolist()
+    else:
+        bf = torch.from_numpy(ref.val.copy()).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+        assert vals.tolist() == bf.tolist()
+
+
+# ------------------------------------------------------------------ exact search
+def test_exact_search_tiny_workload(sindi):
+    """Plain method, exact: 10K docs, vocab 30,522, 100 queries, no pruning, top-10."""
+    from synth.workloads import WORKLOADS
+    wl = WORKLOADS["tiny"]
+    corpus, queries = wl.corpus(), wl.queries()
+    idx = sindi.Index(corpus, alpha=1.0, window=wl.window)
+    ids, sc = idx.search(queries, wl.k, gamma=wl.gamma)
+    ids, sc = _np(ids), _np(sc)
+    ref_ids, ref_sc = oracle.exact_topk(corpus, queries, wl.k)
+    check_ranked(ids, sc)
+    check_scores(corpus, queries, ids, sc, rtol=1e-5)
+    check_same_topk(ids, ref_ids, ref_sc, _tol_kth(corpus, queries, ref_ids, ref_sc, 1e-5))
+    assert oracle.recall_at_k(ids, ref_ids) >= 0.99
+
+
+def test_exact_search_signed_values_and_ragged_tiles(sindi):
+    rng = np.random.default_rng(21)
+    corpus = synth.random_csr(rng, 5_003, 300, 30, signed=True)
+    queries = synth.random_csr(rng, 40, 300, 15, signed=True)
+    idx = sindi.Index(corpus, alpha=1.0, window=1_234, tile=500)
+    for k in (1, 7, 33):
+        ids, sc = idx.search(queries, k, gamma=k)
+        ids, sc = _np(ids), _np(sc)
+        ref_ids, ref_sc = oracle.exact_topk(corpus, queries, k)
+        check_ranked(ids, sc)
+        check_scores(corpus, queries, ids, sc, rtol=1e-5)
+        check_same_topk(ids, ref_ids, ref_sc, _tol_kth(corpus, queries, ref_ids, ref_sc, 1e-5))
+
+
+def test_paper_worked_example_on_gpu(sindi):
+    g = load_golden("paper_search_example.json")
+    f = g["filled_in_not_printed"]
+    corpus = csr_from_dict_rows(f["docs"], 9, g["n_cols"])
+    q = synth.Csr(np.array([0, 3], np.int64), np.array([1, 5, 8], np.int32),
+                  np.array([g["derived"]["q1"], f["q5"], f["q8"]], np.float32), g["n_cols"])
+    idx = sindi.Index(corpus, alpha=1.0, window=9)
+    ids, sc = idx.search(q, 9, gamma=9)
+    ids, sc = _np(ids)[0], _np(sc)[0]
+    assert ids[0] == g["printed_in_paper"]["argmax_doc"]
+    assert sc[0] == pytest.approx(g["printed_in_paper"]["A4_final"], rel=1e-6)
+    assert sorted(int(i) for i, s in zip(ids, sc) if s != 0) == g["printed_in_paper"]["touched_docs"]
+    cid, csc = idx.search_coarse(q, 1)
+    assert int(_np(cid)[0, 0]) == 4 and float(_np(csc)[0, 0]) == pytest.approx(36.1, rel=1e-6)
+
+
+# ------------------------------------------------------------------ Alg. 2 / Alg. 4
+def _pool_margin(pool_ids, pool_sc, corpus_pruned, queries_pruned, rtol):
+    """Near-tie test at the rerank-pool boundary on oracle coarse scores."""
+    gam = pool_ids.shape[1]
+
+    def f(r, d):
+        valid = pool_ids[r] >= 0
+        last = pool_sc[r][valid][-1]
+        lastid = pool_ids[r][valid][-1]
+        c = oracle.pair_scores(corpus_pruned, queries_pruned, [r], [d])[0]
+        sc = score_scale(corpus_pruned, queries_pruned, [r, r], [d, lastid]).max()
+        return abs(c - last) <= 2 * rtol * sc + 1e-30
+    return f
+
+
+@pytest.mark.parametrize("dtype,coarse_rtol", [("f32", 1e-5), ("f16", 2e-3), ("bf16", 8e-3)])
+def test_approximate_search_matches_alg4(sindi, small, dtype, coarse_rtol):
+    corpus, queries = small
+    alpha, beta, gamma, k = 0.5, 0.8, 100, 10
+    idx = sindi.Index(corpus, alpha=alpha, window=WINDOW, value_dtype=dtype, tile=TILE)
+    ids, sc = idx.search(queries, k, beta=beta, gamma=gamma, cand_cap=2048)
+    ids, sc = _np(ids), _np(sc)
+    keep = oracle.mass_prune(corpus, alpha)
+    ref = oracle.build_index(corpus, WINDOW, keep)
+    rid, rsc, pid, psc = oracle.approx_search(ref, corpus, queries, beta, gamma, k, want_pool=True)
+    check_ranked(ids, sc)
+    check_scores(corpus, queries, ids, sc, rtol=1e-5)  # FP32 rerank from unpruned rows
+    cp = oracle.apply_mask(corpus, keep)
+    qp = oracle.apply_mask(queries, oracle.mass_prune(queries, beta))
+    check_same_topk(ids, rid, rsc, _tol_kth(corpus, queries, rid, rsc, 1e-5),
+                    pool_margin=_pool_margin(pid, psc, cp, qp, coarse_rtol))
+
+
+@pytest.mark.parametrize("dtype,rtol", [("f32", 1e-5), ("f16", 2e-3)])
+def test_coarse_search_matches_alg2(sindi, small, dtype, rtol):
+    corpus, queries = small
+    alpha, k = 0.5, 50
+    idx = sindi.Index(corpus, alpha=alpha, window=WINDOW, value_dtype=dtype, tile=TILE)
+    ids, sc = idx.search_coarse(queries, k)
+    ids, sc = _np(ids), _np(sc)
+    keep = oracle.mass_prune(corpus, alpha)
+    cp = oracle.apply_mask(corpus, keep)
+    rid, rsc = oracle.precise_search(oracle.build_index(corpus, WINDOW, keep), queries, k)
+    check_ranked(ids, sc)
+    check_scores(cp, queries, ids, sc, rtol=rtol)
+    check_same_topk(ids, rid, rsc, _tol_kth(cp, queries, rid, rsc, rtol))
+
+
+def test_threshold_paths_agree(sindi, small):
+    """Keep-all, sampled threshold and the forced retry give the same pool and results."""
+    corpus, queries = small
+    idx = sindi.Index(corpus, alpha=0.5, window=WINDOW, tile=TILE)
+    base_ids, base_sc = map(_np, idx.search(queries, 20, gamma=200, sample_tiles=-1))
+    for kw in ({"cand_cap": 4096}, {"cand_cap": 4096, "sample_tiles": 3}, {"cand_cap": 200},
+               {"cand_cap": 4096, "batch": 1}):
+        ids, sc = map(_np, idx.search(queries, 20, gamma=200, **kw))
+        same = ids == base_ids
+        assert same.mean() > 0.99, kw
+        np.testing.assert_allclose(sc[same], base_sc[same], rtol=2e-6)
+
+
+@pytest.mark.parametrize("batch", [1, 2, 4, 8])
+def test_batch_size_does_not_change_results(sindi, small, batch):
+    corpus, queries = small
+    idx = sindi.Index(corpus, alpha=0.5, window=WINDOW, tile=TILE)
+    a_ids, a_sc = map(_np, idx.search(queries, 10, gamma=100, batch=1))
+    ids, sc = map(_np, idx.search(queries, 10, gamma=100, batch=batch))
+    assert (ids == a_ids).mean() > 0.99
+    np.testing.assert_allclose(sc[ids == a_ids], a_sc[ids == a_ids], rtol=2e-6)
+
+
+def test_device_resident_queries_match_host_queries(sindi, small):
+    corpus, queries = small
+    idx = sindi.Index(corpus, alpha=0.5, window=WINDOW, tile=TILE)
+    h_ids, h_sc = map(_np, idx.search(queries, 10, gamma=100))
+    d_ids, d_sc = map(_np, idx.search(sindi.DeviceCsr.from_host(queries), 10, gamma=100))
+    assert (h_ids == d_ids).mean() > 0.99
+    np.testing.assert_allclose(d_sc[h_ids == d_ids], h_sc[h_ids == d_ids], rtol=2e-6)
+
+
+# ------------------------------------------------------------------ edge cases
+def test_empty_and_zero_queries_return_lowest_ids(sindi):
+    corpus = synth.generate(3_000, 500, nnz=("poisson", 10.0), seed=3)
+    q = synth.Csr(np.array([0, 0, 2, 3], np.int64), np.array([4, 9, 499], np.int32),
+                  np.array([0.0, 0.0, 1.0], np.float32), 500)
+    idx = sindi.Index(corpus, alpha=0.5, window=1_000, tile=300)
+    ids, sc = map(_np, idx.search(q, 5, gamma=20))
+    for r in (0, 1):
+        assert ids[r].tolist() == [0, 1, 2, 3, 4] and (sc[r] == 0).all()
+    ref_ids, ref_sc = oracle.exact_topk(corpus, q, 5)
+    check_scores(corpus, q, ids, sc, rtol=1e-5)
+
+
+def test_k_larger_than_corpus_pads(sindi):
+    corpus = synth.generate(5, 50, nnz=("poisson", 5.0), seed=4)
+    q = synth.generate(3, 50, nnz=("poisson", 5.0), seed=4, stream=1)
+    idx = sindi.Index(corpus, alpha=1.0, window=2)
+    ids, sc = map(_np, idx.search(q, 8, gamma=8))
+    ref_ids, ref_sc = oracle.exact_topk(corpus, q, 8)
+    assert (ids[:, 5:] == -1).all() and np.isneginf(sc[:, 5:]).all()
+    check_ranked(ids, sc)
+    check_same_topk(ids, ref_ids, ref_sc, np.full(3, 1e-5))
+
+
+def test_window_of_one_document(sindi):
+    corpus = synth.generate(700, 80, nnz=("poisson", 6.0), seed=5)
+    q = synth.generate(10, 80, nnz=("poisson", 4.0), seed=5, stream=1)
+    idx = sindi.Index(corpus, alpha=1.0, window=1)
+    assert idx.info()["n_tiles"] == 700
+    ids, sc = map(_np, idx.search(q, 6, gamma=6))
+    ref_ids, ref_sc = oracle.exact_topk(corpus, q, 6)
+    check_same_topk(ids, ref_ids, ref_sc, _tol_kth(corpus, q, ref_ids, ref_sc, 1e-5))
+
+
+def test_explicit_zeros_are_absent_entries(sindi):
+    corpus = synth.generate(2_000, 300, nnz=("poisson", 20.0), seed=6)
+    z = corpus.values.copy()
+    z[::7] = 0.0
+    cz = synth.Csr(corpus.indptr, corpus.indices, z, 300)
+    q = synth.generate(20, 300, nnz=("poisson", 8.0), seed=6, stream=1)
+    idx = sindi.Index(cz, alpha=0.6, window=500, tile=256)
+    ids, sc = map(_np, idx.search(q, 10, gamma=60))
+    nz = cz.values != 0
+    stripped = oracle.apply_mask(cz, nz.astype(np.uint8))
+    keep_s = oracle.mass_prune(stripped, 0.6)
+    ref = oracle.build_index(stripped, 500, keep_s)
+    rid, rsc = oracle.approx_search(ref, stripped, q, 1.0, 60, 10)
+    check_scores(stripped, q, ids, sc, rtol=1e-5)
+    check_same_topk(ids, rid, rsc, _tol_kth(stripped, q, rid, rsc, 1e-5))
+
+
+def test_invalid_queries_raise_and_leave_outputs(sindi):
+    corpus = synth.generate(500, 100, nnz=("poisson", 8.0), seed=7)
+    idx = sindi.Index(corpus, alpha=1.0, window=500)
+    bad = synth.Csr(np.array([0, 2], np.int64), np.array([5, 3], np.int32),
+                    np.array([1.0, 1.0], np.float32), 100)
+    out = (torch.full((1, 4), 7, dtype=torch.int64, device="cuda"),
+           torch.full((1, 4), 7.0, device="cuda"))
+    with pytest.raises(sindi.SindiError, match="ascending"):
+        idx.search(bad, 4, gamma=4, out=out)
+    with pytest.raises(sindi.SindiError, match="malformed"):
+        idx.search(sindi.DeviceCsr.from_host(bad), 4, gamma=4, out=out)
+    assert (out[0] == 7).all() and (out[1] == 7.0).all()
+    wrong_cols = synth.Csr(np.array([0, 1], np.int64), np.array([1], np.int32),
+                           np.array([1.0], np.float32), 99)
+    with pytest.raises(sindi.SindiError, match="columns"):
+        idx.search(wrong_cols, 4)
+    with pytest.raises(sindi.SindiError, match="gamma"):
+        idx.search(bad, 10, gamma=5)
+
+
+# ------------------------------------------------------------------ pair scores and gradients
+def test_score_forward_backward_against_oracle(sindi):
+    corpus = synth.generate(4_000, 3_000, nnz=("poisson", 60.0), seed=8)
+    queries = synth.generate(16, 3_000, nnz=("poisson", 20.0), seed=8, stream=1)
+    idx = sindi.Index(corpus, alpha=1.0, window=4_000)
+    rng = np.random.default_rng(8)
+    cand = np.stack([rng.choice(4_000, size=25, replace=False) for _ in range(16)]).astype(np.int64)
+    cand[0, 3] = -1
+    dq = sindi.DeviceCsr.from_host(queries)
+    s = _np(idx.score(dq, torch.from_numpy(cand).cuda()))
+    qrows = np.repeat(np.arange(16), 25)
+    exact = oracle.pair_scores(corpus, queries, qrows, cand.reshape(-1)).reshape(16, 25)
+    exact[0, 3] = 0.0
+    np.testing.assert_allclose(s, exact, rtol=1e-5, atol=1e-6)
+    G = rng.standard_normal((16, 25))
+    gq = torch.zeros(queries.nnz, device="cuda")
+    gx = torch.zeros(corpus.nnz, device="cuda")
+    idx.score_backward(dq, torch.from_numpy(cand).cuda(), torch.from_numpy(G).float().cuda(), gq, gx)
+    rq, rx = oracle.score_grad(corpus, queries, cand, G.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(_np(gq), rq, rtol=1e-5, atol=1e-5 * np.abs(rq).max())
+    np.testing.assert_allclose(_np(gx), rx, rtol=1e-5, atol=1e-5 * np.abs(rx).max())
