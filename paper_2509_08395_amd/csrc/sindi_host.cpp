@@ -162,10 +162,10 @@ struct sindi_index {
     int device = 0;
     int64_t max_lds = 0;
     std::vector<int64_t> h_tile_doc;
-    DBuf indptr, indices, values, tile_doc, tile_post, term_off, post_doc, post_val;
+    DBuf indptr, indices, values, tile_doc, tile_post, term_off, post_doc, post_val, term_max;
     // search workspace, guarded by mu
     std::mutex mu;
-    DBuf q_ptr, q_idx, q_val, ct, cw, cn, sabs, err, status, slot_q, maxima, theta, count, cand;
+    DBuf q_ptr, q_idx, q_val, ct, cw, cn, qinv, sabs, err, status, slot_q, maxima, theta, count, cand;
 
     DevIndex dev() const
     {
@@ -180,6 +180,7 @@ struct sindi_index {
         d.term_off = term_off.as<uint32_t>();
         d.post_doc = post_doc.as<uint16_t>();
         d.post_val = post_val.p;
+        d.term_max = term_max.as<float>();
         d.indptr = indptr.as<int64_t>();
         d.indices = indices.as<int32_t>();
         d.values = values.as<float>();
@@ -189,7 +190,8 @@ struct sindi_index {
     int64_t device_bytes() const
     {
         return (int64_t)(indptr.bytes + indices.bytes + values.bytes + tile_doc.bytes +
-                         tile_post.bytes + term_off.bytes + post_doc.bytes + post_val.bytes);
+                         tile_post.bytes + term_off.bytes + post_doc.bytes + post_val.bytes +
+                         term_max.bytes);
     }
 };
 
@@ -325,7 +327,7 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     ix->n_tiles = n_tiles;
     ix->tile_max = tmax;
     ix->tile_stride = std::max<int32_t>(4, (tmax + 3) / 4 * 4);
-    if ((int64_t)ix->tile_stride * 4 + (5 * kEntryBlock + 1) * 4 > ix->max_lds)
+    if ((int64_t)accumulate_lds_bytes(1, ix->tile_stride) > ix->max_lds)
         return fail(SINDI_E_INVALID, "sindi_build: tile of %d documents exceeds on-chip memory",
                     tmax);
 
@@ -396,6 +398,26 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
         }
     });
 
+    // largest |stored value| per term: bounds every coarse partial sum
+    std::vector<float> term_max((size_t)nc, 0.0f);
+    {
+        std::mutex mx;
+        parallel_for(nd, [&](int64_t lo, int64_t hi) {
+            std::vector<float> m((size_t)nc, 0.0f);
+            for (int64_t i = lo; i < hi; ++i)
+                for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e) {
+                    if (!keep[e]) continue;
+                    float v = c->values[e];
+                    if (p->value_dtype == SINDI_F16) v = (float)__builtin_bit_cast(_Float16, to_f16(v));
+                    else if (p->value_dtype == SINDI_BF16)
+                        v = __builtin_bit_cast(float, (uint32_t)to_bf16(v) << 16);
+                    m[c->indices[e]] = std::max(m[c->indices[e]], std::fabs(v));
+                }
+            std::lock_guard<std::mutex> g(mx);
+            for (int64_t j = 0; j < nc; ++j) term_max[j] = std::max(term_max[j], m[j]);
+        });
+    }
+
     // upload: unpruned corpus (Alg. 3 returns D too) and the tiled lists
     auto up = [&](DBuf &b, const void *src, size_t bytes) -> hipError_t {
         hipError_t e = b.ensure(bytes);
@@ -417,6 +439,7 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     if ((st = up_or_fail(ix->term_off, term_off.data(), term_off.size() * 4, "term offsets")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->post_doc, post_doc.data(), post_doc.size() * 2, "posting ids")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->post_val, post_val.data(), post_val.size(), "posting values")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->term_max, term_max.data(), term_max.size() * 4, "term maxima")) != SINDI_OK) return st;
     HIP_TRY(hipStreamSynchronize(s));
     ix->h_tile_doc = std::move(tile_doc);
     *out = guard.release();
@@ -428,7 +451,7 @@ int pick_batch(const sindi_index *ix, int32_t req)
 {
     int b = req ? req : kDefaultBatch;
     if (b != 1 && b != 2 && b != 4 && b != 8) return -1;
-    while (b > 1 && (int64_t)b * ix->tile_stride * 4 + (5 * kEntryBlock + 1) * 4 > ix->max_lds) b >>= 1;
+    while (b > 1 && (int64_t)accumulate_lds_bytes(b, ix->tile_stride) > ix->max_lds) b >>= 1;
     return b;
 }
 
@@ -479,12 +502,16 @@ sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
     HIP_TRY(ix->ct.ensure((size_t)qc->nnz * 4 + 4));
     HIP_TRY(ix->cw.ensure((size_t)qc->nnz * 4 + 4));
     HIP_TRY(ix->cn.ensure((size_t)nq * 4));
+    HIP_TRY(ix->qinv.ensure((size_t)nq * 4));
     HIP_TRY(ix->sabs.ensure(beta < 1.0 ? (size_t)qc->nnz * 8 + 8 : 8));
     HIP_TRY(ix->err.ensure(4));
     HIP_TRY(ix->status.ensure((size_t)nq * 4));
     HIP_TRY(launch_fill_u32(ix->err.as<uint32_t>(), 1, 0u, s));
-    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>()};
-    HIP_TRY(timed(kProfPrep, s, [&] { return launch_query_prep(dq, ix->n_cols, beta, dc, ix->sabs.as<double>(), ix->err.as<int32_t>(), s); }));
+    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>(), ix->qinv.as<float>()};
+    HIP_TRY(timed(kProfPrep, s, [&] {
+        return launch_query_prep(dq, ix->n_cols, beta, dc, ix->term_max.as<float>(),
+                                 ix->sabs.as<double>(), ix->err.as<int32_t>(), s);
+    }));
     int32_t qerr = 0;
     HIP_TRY(hipMemcpyAsync(&qerr, ix->err.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -608,10 +635,12 @@ sindi_status check_dev_queries(sindi_index *ix, const sindi_csr *qc, const char 
     HIP_TRY(ix->ct.ensure((size_t)qc->nnz * 4 + 4));
     HIP_TRY(ix->cw.ensure((size_t)qc->nnz * 4 + 4));
     HIP_TRY(ix->cn.ensure((size_t)qc->n_rows * 4));
+    HIP_TRY(ix->qinv.ensure((size_t)qc->n_rows * 4));
     HIP_TRY(ix->err.ensure(4));
     HIP_TRY(launch_fill_u32(ix->err.as<uint32_t>(), 1, 0u, s));
-    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>()};
-    HIP_TRY(launch_query_prep(dq, ix->n_cols, 1.0, dc, nullptr, ix->err.as<int32_t>(), s));
+    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>(), ix->qinv.as<float>()};
+    HIP_TRY(launch_query_prep(dq, ix->n_cols, 1.0, dc, ix->term_max.as<float>(), nullptr,
+                              ix->err.as<int32_t>(), s));
     int32_t qerr = 0;
     HIP_TRY(hipMemcpyAsync(&qerr, ix->err.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

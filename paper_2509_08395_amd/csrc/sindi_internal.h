@@ -13,13 +13,14 @@ namespace sindi {
 // unpruned corpus kept for the exact rerank of Alg. 4.
 struct DevIndex {
     int64_t n_docs, n_cols, n_tiles;
-    int32_t tile_stride;           // floats per query row of the on-chip score tile (>= tile_max, %4 == 0)
+    int32_t tile_stride;           // words per query row of the on-chip score tile (>= tile_max, %4 == 0)
     int32_t value_dtype;           // sindi_dtype
     const int64_t *tile_doc;       // [n_tiles + 1] first document of each tile
     const int64_t *tile_post;      // [n_tiles + 1] first posting of each tile
     const uint32_t *term_off;      // [n_tiles * (n_cols + 1)] list starts relative to tile_post[t]
     const uint16_t *post_doc;      // [n_postings + pad] document id - tile_doc[t]
     const void *post_val;          // [n_postings + pad] value (f32 / f16 / bf16 bits)
+    const float *term_max;         // [n_cols] largest |stored value| in the term's lists
     const int64_t *indptr;         // unpruned corpus CSR, [n_docs + 1]
     const int32_t *indices;        // [nnz]
     const float *values;           // [nnz]
@@ -36,26 +37,40 @@ struct DevQueries {
 
 // Per-query coarse terms (beta-mass subvector, ascending term id), stored at
 // the query row's own positions: terms ct[indptr[q] + i], weights cw[...],
-// i < cn[q].
+// i < cn[q].  Coarse scores are accumulated as 32-bit integers in units of
+// 1/scale_q, scale_q a power of two with scale_q * sum_i |q_i| max|x_i| <=
+// 2^30, so no partial sum can overflow; cw holds q_i * scale_q and
+// qinv[q] = 1 / scale_q.
 struct DevCoarse {
     int32_t *ct;
     float *cw;
     int32_t *cn;
+    float *qinv;
 };
 
-constexpr int kAccThreads = 512;       // accumulate kernel workgroup
+constexpr int kAccThreads = 1024;      // accumulate kernel workgroup
 constexpr int kFinThreads = 256;       // finalize / theta kernels
 constexpr int kGammaMax = 4096;        // largest reorder pool
 constexpr int kQueryHash = 8192;       // rerank hash slots (query nnz <= kQueryHash / 2)
-constexpr int kEntryBlock = 512;       // (query, term) entries staged per pass in the accumulate kernel
-constexpr int kChunkGroups = 128;      // 4-posting groups per work chunk (2 per lane)
+constexpr int kEntryBlock = 1024;      // (query, term) entries merged per pass in the accumulate kernel
+constexpr int kUnroll = 4;             // 4-posting groups in flight per lane
+
+// LDS of one accumulate workgroup: the score rows A[batch][tile_stride], the
+// batch's merged term list (ids + one weight per query) and a region that
+// first holds the merge sort keys, then the per-tile list bounds.
+inline size_t accumulate_lds_bytes(int batch, int tile_stride)
+{
+    return (size_t)batch * tile_stride * 4 + (size_t)kEntryBlock * 4 +
+           (size_t)kEntryBlock * batch * 4 + ((size_t)3 * kEntryBlock + 4) * 4;
+}
 
 // Status codes written per query slot by the finalize kernel.
 enum SlotStatus : int32_t { kSlotOk = 0, kSlotRetry = 1 };
 
 // Kernel launchers (sindi_kernels.hip).  All return hipGetLastError().
 hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, DevCoarse c,
-                             double *scratch_abs, int32_t *err_flag, hipStream_t s);
+                             const float *term_max, double *scratch_abs, int32_t *err_flag,
+                             hipStream_t s);
 
 hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                              int batch, bool sample, const int32_t *slot_q, int32_t n_slots,

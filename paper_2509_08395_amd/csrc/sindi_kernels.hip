@@ -52,6 +52,12 @@ __device__ __forceinline__ void lds_add(float *p, float v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// Integer LDS atomics run at many times the rate of float ones on gfx950.
+__device__ __forceinline__ void lds_add_i32(int32_t *p, int32_t v)
+{
+    __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(p), (uint32_t)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -132,9 +138,11 @@ __device__ K block_select(int64_t n, int64_t r, Load load, uint32_t *hist, int *
 // 16 more than kQueryHash / 2 entries)
 // and writes the coarse terms: the non-zero entries, cut to the beta-mass
 // subvector when beta < 1 (entries ranked by |q| descending, ties by id;
-// FP64 prefix sums in that order, the first prefix reaching beta * mass).
+// FP64 prefix sums in that order, the first prefix reaching beta * mass),
+// with weights pre-multiplied by the query's fixed-point scale.
 __global__ __launch_bounds__(256) void k_query_prep(DevQueries q, int64_t n_cols, double beta,
-                                                    DevCoarse c, double *sabs, int32_t *err)
+                                                    DevCoarse c, const float *term_max,
+                                                    double *sabs, int32_t *err)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x / kWave);
@@ -159,6 +167,7 @@ __global__ __launch_bounds__(256) void k_query_prep(DevQueries q, int64_t n_cols
         if (lane == 0) {
             atomicOr(err, bad);
             c.cn[row] = 0;
+            c.qinv[row] = 1.0f;
         }
         return;
     }
@@ -230,15 +239,39 @@ __global__ __launch_bounds__(256) void k_query_prep(DevQueries q, int64_t n_cols
         }
         base += __popcll(m);
     }
-    if (lane == 0) c.cn[row] = base;
+    // fixed-point scale: the largest power of two keeping every partial
+    // coarse sum of this query within 2^30 in magnitude
+    float bound = 0.0f;
+    for (int32_t i = lane; i < base; i += kWave)
+        bound += fabsf(c.cw[a + i]) * term_max[c.ct[a + i]];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) bound += __shfl_xor(bound, m, kWave);
+    int ex = 0;
+    if (bound > 0.0f) {
+        (void)frexpf(bound, &ex);  // bound < 2^ex
+        ex = 30 - ex;
+        ex = ex > 100 ? 100 : (ex < -100 ? -100 : ex);
+    }
+    const float scale = ldexpf(1.0f, ex);
+    for (int32_t i = lane; i < base; i += kWave) c.cw[a + i] *= scale;
+    if (lane == 0) {
+        c.cn[row] = base;
+        c.qinv[row] = ldexpf(1.0f, -ex);
+    }
 }
 
 // ------------------------------------------------------------------ accumulate
+// Posting values: raw bits of one aligned 4-posting group, decoded after
+// every load of the step has been issued.
 template <int VT> struct Val;
 template <> struct Val<0> {  // FP32
-    static __device__ __forceinline__ void load(const void *p, uint64_t g, float (&v)[4])
+    using Raw = uint4;
+    static __device__ __forceinline__ Raw load(const void *p, uint64_t g)
     {
-        uint4 r = reinterpret_cast<const uint4 *>(p)[g];
+        return reinterpret_cast<const uint4 *>(p)[g];
+    }
+    static __device__ __forceinline__ void decode(const Raw &r, float (&v)[4])
+    {
         v[0] = __uint_as_float(r.x);
         v[1] = __uint_as_float(r.y);
         v[2] = __uint_as_float(r.z);
@@ -246,13 +279,17 @@ template <> struct Val<0> {  // FP32
     }
 };
 template <> struct Val<1> {  // FP16
+    using Raw = uint2;
+    static __device__ __forceinline__ Raw load(const void *p, uint64_t g)
+    {
+        return reinterpret_cast<const uint2 *>(p)[g];
+    }
     static __device__ __forceinline__ float h2f(uint32_t h)
     {
         return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
     }
-    static __device__ __forceinline__ void load(const void *p, uint64_t g, float (&v)[4])
+    static __device__ __forceinline__ void decode(const Raw &r, float (&v)[4])
     {
-        uint2 r = reinterpret_cast<const uint2 *>(p)[g];
         v[0] = h2f(r.x & 0xFFFFu);
         v[1] = h2f(r.x >> 16);
         v[2] = h2f(r.y & 0xFFFFu);
@@ -260,9 +297,13 @@ template <> struct Val<1> {  // FP16
     }
 };
 template <> struct Val<2> {  // BF16
-    static __device__ __forceinline__ void load(const void *p, uint64_t g, float (&v)[4])
+    using Raw = uint2;
+    static __device__ __forceinline__ Raw load(const void *p, uint64_t g)
     {
-        uint2 r = reinterpret_cast<const uint2 *>(p)[g];
+        return reinterpret_cast<const uint2 *>(p)[g];
+    }
+    static __device__ __forceinline__ void decode(const Raw &r, float (&v)[4])
+    {
         v[0] = __uint_as_float(r.x << 16);
         v[1] = __uint_as_float(r.x & 0xFFFF0000u);
         v[2] = __uint_as_float(r.y << 16);
@@ -270,50 +311,91 @@ template <> struct Val<2> {  // BF16
     }
 };
 
-// One workgroup = one tile of documents x a batch of B query slots.  The
-// tile's score rows A[b][0..len) live in LDS (the window's distance array of
-// Sec. 3.3.1, one row per query).  Work list: for every (query, term) entry,
-// the list I_{term, tile} cut into chunks of kChunkGroups aligned 4-posting
-// groups; waves take chunks round-robin.  Every posting adds
-// q_b^term * x to A[b][doc] (product, then add, as Alg. 2 stores P^j then
-// accumulates).  Different terms may hit one document concurrently, so the
-// adds are LDS atomics.
+template <int B> struct Weights {
+    static __device__ __forceinline__ void read(const float *w, float (&o)[B])
+    {
+#pragma unroll
+        for (int b = 0; b < B; b += 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(w + b);
+            o[b] = x.x;
+            o[b + 1] = x.y;
+            o[b + 2] = x.z;
+            o[b + 3] = x.w;
+        }
+    }
+};
+template <> struct Weights<1> {
+    static __device__ __forceinline__ void read(const float *w, float (&o)[1]) { o[0] = w[0]; }
+};
+template <> struct Weights<2> {
+    static __device__ __forceinline__ void read(const float *w, float (&o)[2])
+    {
+        const float2 x = *reinterpret_cast<const float2 *>(w);
+        o[0] = x.x;
+        o[1] = x.y;
+    }
+};
+
+// One workgroup = a batch of B query slots x a strided set of tiles.  The
+// batch's (query, term) entries are first merged into one ascending list of
+// distinct terms, each with a weight per query (zero where the query lacks
+// the term), so a list I_{term, tile} shared by several queries of the batch
+// is read once.  Then, for every tile: the score rows A[b][0..len) (the
+// window's distance array of Sec. 3.3.1, one row per query) are cleared in
+// LDS; the tile's lists of all merged terms are laid end to end as aligned
+// 4-posting groups and the waves sweep that range, kUnroll groups per lane in
+// flight; every posting adds w_b * x to A[b][doc] for each query b holding
+// the term (Alg. 2: product, then accumulate).  Different terms can hit one
+// document concurrently, so the adds are LDS atomics, on 32-bit integers:
+// each product is rounded once to the query's fixed-point grid (weights
+// arrive pre-scaled), which makes the sums exact, independent of the order
+// of the atomics, and several times faster than float LDS atomics on this
+// chip.  Scores are converted back to FP32 when read.  Finally the rows are
+// either sampled (per-thread maxima, for the candidate threshold) or every
+// score at or above the query's threshold is appended to its candidate list.
 template <int VT, int B, bool SAMPLE>
 __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
     int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
     int64_t cap)
 {
-    constexpr int NT = kAccThreads, NW = NT / kWave;
-    static_assert(kEntryBlock == NT, "one staged entry per thread");
+    constexpr int NT = kAccThreads, NW = NT / kWave, EB = kEntryBlock;
+    static_assert(EB == NT, "one merged entry per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = ix.tile_stride;
-    float *A = reinterpret_cast<float *>(smem);
-    uint32_t *e_lo = reinterpret_cast<uint32_t *>(A + (size_t)B * T);
-    uint32_t *e_hi = e_lo + kEntryBlock;
-    float *e_w = reinterpret_cast<float *>(e_hi + kEntryBlock);
-    uint32_t *e_b = reinterpret_cast<uint32_t *>(e_w + kEntryBlock);
-    uint32_t *cpre = e_b + kEntryBlock;  // kEntryBlock + 1
+    int32_t *A = reinterpret_cast<int32_t *>(smem);  // fixed-point scores
+    int32_t *u_term = A + (size_t)B * T;
+    float *u_w = reinterpret_cast<float *>(u_term + EB);  // [EB][B]
+    unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (size_t)EB * B);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(region);                 // merge phase
+    uint32_t *flag = reinterpret_cast<uint32_t *>(keys + EB);              // merge phase
+    uint32_t *u_gs = reinterpret_cast<uint32_t *>(region);                 // tile phase
+    uint32_t *u_hl = u_gs + EB;
+    uint32_t *gp = u_hl + EB;                                              // EB + 1
     __shared__ int64_t s_qa[B];
     __shared__ int32_t s_qpre[B + 1];
     __shared__ int32_t s_slot[B];
+    __shared__ float s_qinv[B];
     __shared__ uint32_t s_wsum[NW];
+    __shared__ int32_t s_nu;
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int32_t batch = blockIdx.x;
-
     if (tid == 0) {
         int32_t acc = 0;
         for (int b = 0; b < B; ++b) {
-            int32_t s = batch * B + b;
+            const int32_t s = batch * B + b;
             int32_t n = 0;
             int64_t qa = 0;
+            float qinv = 1.0f;
             if (s < n_slots) {
-                int32_t row = slot_q ? slot_q[s] : s;
+                const int32_t row = slot_q[s];
                 qa = q.indptr[row];
                 n = c.cn[row];
+                qinv = c.qinv[row];
             }
             s_slot[b] = s < n_slots ? s : -1;
+            s_qinv[b] = qinv;
             s_qa[b] = qa;
             s_qpre[b] = acc;
             acc += n;
@@ -322,6 +404,61 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     }
     __syncthreads();
     const int32_t n_e = s_qpre[B];
+    const int32_t n_blocks = (n_e + EB - 1) / EB;
+
+    // Merge entries [e0, e0 + EB) of the batch into u_term / u_w (s_nu terms).
+    auto merge = [&](int32_t e0) {
+        const int32_t ne = min(EB, n_e - e0);
+        int P = 1;
+        while (P < ne) P <<= 1;
+        if (tid < P) {
+            uint64_t key = ~0ull;
+            if (tid < ne) {
+                const int32_t e = e0 + tid;
+                int b = 0;
+                while (b + 1 < B && s_qpre[b + 1] <= e) ++b;
+                key = ((uint64_t)(uint32_t)c.ct[s_qa[b] + (e - s_qpre[b])] << 32) | (uint32_t)tid;
+            }
+            keys[tid] = key;
+        }
+        __syncthreads();
+        for (int kk = 2; kk <= P; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                if (tid < P) {
+                    const int ij = tid ^ j;
+                    if (ij > tid) {
+                        const uint64_t x = keys[tid], y = keys[ij];
+                        const bool up = (tid & kk) == 0;
+                        if (up ? (x > y) : (x < y)) {
+                            keys[tid] = y;
+                            keys[ij] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        const uint32_t fresh =
+            (tid < ne && (tid == 0 || (keys[tid] >> 32) != (keys[tid - 1] >> 32))) ? 1u : 0u;
+        uint32_t nu;
+        const uint32_t ex = block_excl_scan<NT>(fresh, s_wsum, nu);
+        for (int i = tid; i < (int)nu * B; i += NT) u_w[i] = 0.0f;
+        flag[tid] = ex + fresh;  // 1-based merged index of this sorted entry's term
+        if (tid == 0) s_nu = (int32_t)nu;
+        __syncthreads();
+        if (tid < ne) {
+            const uint64_t key = keys[tid];
+            const int32_t u = (int32_t)flag[tid] - 1;
+            const int32_t e = e0 + (int32_t)(key & 0xFFFFFFFFu);
+            int b = 0;
+            while (b + 1 < B && s_qpre[b + 1] <= e) ++b;
+            if (fresh) u_term[u] = (int32_t)(key >> 32);
+            u_w[u * B + b] = c.cw[s_qa[b] + (e - s_qpre[b])];
+        }
+        __syncthreads();
+    };
+
+    if (n_blocks == 1) merge(0);
     const int64_t n_tile_iter = SAMPLE ? n_sample : ix.n_tiles;
 
     for (int64_t ti = blockIdx.y; ti < n_tile_iter; ti += gridDim.y) {
@@ -331,70 +468,97 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
         const uint64_t P0 = (uint64_t)ix.tile_post[t];
         const uint32_t *toff = ix.term_off + (size_t)t * (size_t)(ix.n_cols + 1);
 
-        float4 *A4 = reinterpret_cast<float4 *>(A);
-        for (int i = tid; i < B * T / 4; i += NT) A4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        int4 *A4 = reinterpret_cast<int4 *>(A);
+        for (int i = tid; i < B * T / 4; i += NT) A4[i] = make_int4(0, 0, 0, 0);
         __syncthreads();
 
-        for (int32_t eb = 0; eb < n_e; eb += kEntryBlock) {
-            const int32_t ne = min(kEntryBlock, n_e - eb);
-            uint32_t nch = 0;
-            if (tid < ne) {
-                const int32_t e = eb + tid;
-                int b = 0;
-                while (b + 1 < B && s_qpre[b + 1] <= e) ++b;
-                const int64_t pos = s_qa[b] + (e - s_qpre[b]);
-                const int32_t term = c.ct[pos];
+        for (int32_t blk = 0; blk < n_blocks; ++blk) {
+            if (n_blocks > 1) merge(blk * EB);
+            const int32_t nu = s_nu;
+            // list (term, tile) = postings [P0 + lo, P0 + hi); as aligned groups it
+            // starts at group gs and covers positions [lr, hr) counted from 4 * gs
+            uint32_t ng = 0, gs = 0, hl = 0;
+            if (tid < nu) {
+                const int32_t term = u_term[tid];
                 const uint32_t lo = toff[term], hi = toff[term + 1];
-                e_lo[tid] = lo;
-                e_hi[tid] = hi;
-                e_w[tid] = c.cw[pos];
-                e_b[tid] = (uint32_t)b;
                 if (hi > lo) {
-                    const uint64_t g0 = (P0 + lo) >> 2, g1 = (P0 + hi + 3) >> 2;
-                    nch = (uint32_t)((g1 - g0 + kChunkGroups - 1) / kChunkGroups);
+                    const uint64_t a = P0 + lo;
+                    gs = (uint32_t)(a >> 2);
+                    const uint32_t lr = (uint32_t)(a & 3u), hr = lr + (hi - lo);
+                    ng = (hr + 3u) >> 2;
+                    hl = hr | (lr << 30);
                 }
             }
             uint32_t total;
-            const uint32_t ex = block_excl_scan<NT>(nch, s_wsum, total);
-            cpre[tid] = ex;
-            if (tid == 0) cpre[ne] = total;
+            const uint32_t ex = block_excl_scan<NT>(ng, s_wsum, total);
+            // the scan's barriers order these writes after the merge-phase reads
+            if (tid < nu) {
+                u_gs[tid] = gs;
+                u_hl[tid] = hl;
+            }
+            gp[tid] = ex;
+            if (tid == 0) gp[nu] = total;
             __syncthreads();
 
-            for (uint32_t ch = wave; ch < total; ch += NW) {
-                int lo_ = 0, hi_ = ne - 1;
-                while (lo_ < hi_) {
-                    const int mid = (lo_ + hi_ + 1) >> 1;
-                    if (cpre[mid] <= ch) lo_ = mid; else hi_ = mid - 1;
+            constexpr int STEP = kWave * kUnroll;
+            using Raw = typename Val<VT>::Raw;
+            for (uint32_t base = (uint32_t)wave * STEP; base < total; base += (uint32_t)NW * STEP) {
+                const uint32_t last = min(base + (uint32_t)STEP, total) - 1u;
+                int u0, u1;
+                {  // entries holding the first and the last group of this step
+                    int l = 0, h = nu - 1;
+                    while (l < h) {
+                        const int m = (l + h + 1) >> 1;
+                        if (gp[m] <= base) l = m; else h = m - 1;
+                    }
+                    u0 = l;
+                    h = nu - 1;
+                    while (l < h) {
+                        const int m = (l + h + 1) >> 1;
+                        if (gp[m] <= last) l = m; else h = m - 1;
+                    }
+                    u1 = l;
                 }
-                const int u = lo_;
-                const uint64_t plo = P0 + e_lo[u], phi = P0 + e_hi[u];
-                const uint64_t gbeg = (plo >> 2) + (uint64_t)(ch - cpre[u]) * kChunkGroups;
-                const uint64_t glim = (phi + 3) >> 2;
-                const uint64_t gend = glim < gbeg + kChunkGroups ? glim : gbeg + kChunkGroups;
-                const float w = e_w[u];
-                float *Ab = A + (size_t)e_b[u] * T;
-                constexpr int G = kChunkGroups / kWave;
-                uint2 ids[G];
-                float v[G][4];
+                uint2 ids[kUnroll];
+                Raw raw[kUnroll];
+                int uu[kUnroll];
+                uint32_t jj[kUnroll];
 #pragma unroll
-                for (int i = 0; i < G; ++i) {
-                    const uint64_t g = gbeg + (uint64_t)(i * kWave + lane);
-                    if (g < gend) {
+                for (int i = 0; i < kUnroll; ++i) {
+                    const uint32_t vg = base + (uint32_t)(i * kWave + lane);
+                    uu[i] = -1;
+                    if (vg < total) {
+                        int l = u0, h = u1;
+                        while (l < h) {
+                            const int m = (l + h + 1) >> 1;
+                            if (gp[m] <= vg) l = m; else h = m - 1;
+                        }
+                        uu[i] = l;
+                        jj[i] = vg - gp[l];
+                        const uint64_t g = (uint64_t)u_gs[l] + jj[i];
                         ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g];
-                        Val<VT>::load(ix.post_val, g, v[i]);
+                        raw[i] = Val<VT>::load(ix.post_val, g);
                     }
                 }
 #pragma unroll
-                for (int i = 0; i < G; ++i) {
-                    const uint64_t g = gbeg + (uint64_t)(i * kWave + lane);
-                    if (g < gend) {
-                        const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16,
-                                                ids[i].y & 0xFFFFu, ids[i].y >> 16};
+                for (int i = 0; i < kUnroll; ++i) {
+                    const int u = uu[i];
+                    if (u < 0) continue;
+                    const uint32_t hl = u_hl[u];
+                    const uint32_t lr = hl >> 30, hr = hl & 0x3FFFFFFFu, r0 = 4u * jj[i];
+                    float w[B];
+                    Weights<B>::read(u_w + (size_t)u * B, w);
+                    float v[4];
+                    Val<VT>::decode(raw[i], v);
+                    const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16, ids[i].y & 0xFFFFu,
+                                            ids[i].y >> 16};
 #pragma unroll
-                        for (int p = 0; p < 4; ++p) {
-                            const uint64_t pos = 4 * g + p;
-                            if (pos >= plo && pos < phi) lds_add(&Ab[d4[p]], w * v[i][p]);
-                        }
+                    for (int p = 0; p < 4; ++p) {
+                        if (r0 + p < lr || r0 + p >= hr) continue;
+#pragma unroll
+                        for (int b = 0; b < B; ++b)
+                            if (w[b] != 0.0f)
+                                lds_add_i32(&A[(size_t)b * T + d4[p]], __float2int_rn(w[b] * v[p]));
                     }
                 }
             }
@@ -404,20 +568,23 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
         for (int b = 0; b < B; ++b) {
             const int32_t slot = s_slot[b];
             if (slot < 0) continue;
-            const float *Ar = A + (size_t)b * T;
+            const int32_t *Ar = A + (size_t)b * T;
+            const float qinv = s_qinv[b];
             if (SAMPLE) {
-                float mx = -INFINITY;
-                for (int m = tid; m < len; m += NT) mx = fmaxf(mx, Ar[m]);
-                maxima[((size_t)slot * n_sample + ti) * NT + tid] = mx;
+                int32_t mx = INT32_MIN;
+                for (int m = tid; m < len; m += NT) mx = max(mx, Ar[m]);
+                maxima[((size_t)slot * n_sample + ti) * NT + tid] =
+                    tid < len ? (float)mx * qinv : -INFINITY;
             } else {
                 const float th = theta[slot];
                 uint32_t *cnt = count + slot;
                 uint64_t *out = cand + (size_t)slot * (size_t)cap;
                 for (int base = wave * 256; base < len; base += NW * 256) {
                     const int m0 = base + lane * 4;
-                    float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (m0 < len) s4 = *reinterpret_cast<const float4 *>(Ar + m0);
-                    const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+                    int4 s4 = make_int4(0, 0, 0, 0);
+                    if (m0 < len) s4 = *reinterpret_cast<const int4 *>(Ar + m0);
+                    const float sv[4] = {(float)s4.x * qinv, (float)s4.y * qinv,
+                                         (float)s4.z * qinv, (float)s4.w * qinv};
                     bool pr[4];
                     uint64_t bal[4];
                     uint32_t tot = 0;
@@ -448,10 +615,10 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
 }
 
 // ------------------------------------------------------------------ threshold
-// theta = the rank-th largest sampled maximum, lowered by 2^-12 of its
-// magnitude so that FP32 summation-order differences between the sampling
-// and the scoring pass cannot lift a document out of the kept set.  The
-// finalize kernel verifies the result (at least gamma candidates kept).
+// theta = the rank-th largest sampled maximum.  Both accumulate passes
+// produce bitwise identical scores (integer sums), so every sampled document
+// at or above theta is kept again by the scoring pass.  The finalize kernel
+// verifies the result (at least gamma candidates kept).
 __global__ __launch_bounds__(kFinThreads) void k_theta(const float *maxima, int64_t n_m,
                                                        int64_t rank, float *theta)
 {
@@ -462,10 +629,8 @@ __global__ __launch_bounds__(kFinThreads) void k_theta(const float *maxima, int6
     const uint32_t key = block_select<uint32_t>(
         n_m, rank, [&](int64_t i) { return ord_f32(mx[i]); }, hist, &s_digit, &s_need);
     if (threadIdx.x == 0) {
-        float th = unord_f32(key);
-        if (!(th > -INFINITY)) th = -INFINITY;
-        else th = th - fabsf(th) * (1.0f / 4096.0f);
-        theta[blockIdx.x] = th;
+        const float th = unord_f32(key);
+        theta[blockIdx.x] = th > -INFINITY ? th : -INFINITY;
     }
 }
 
@@ -700,13 +865,18 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
                           const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
                           hipStream_t s)
 {
-    const size_t lds = (size_t)B * ix.tile_stride * sizeof(float) +
-                       (size_t)(5 * kEntryBlock + 1) * sizeof(uint32_t);
+    const size_t lds = accumulate_lds_bytes(B, ix.tile_stride);
     hipError_t e = set_lds(k_accumulate<VT, B, SAMPLE>, lds);
     if (e != hipSuccess) return e;
     const int64_t n_batches = (n_slots + B - 1) / B;
-    const int64_t ny = SAMPLE ? n_sample : ix.n_tiles;
-    dim3 grid((unsigned)n_batches, (unsigned)(ny < 65535 ? ny : 65535));
+    const int64_t n_iter = SAMPLE ? n_sample : ix.n_tiles;
+    // Tiles are dealt to workgroups round-robin: enough workgroups to fill the
+    // chip several times over, each sweeping its tiles in ascending order so
+    // that the workgroups in flight read the same tiles' lists at the same time.
+    int64_t groups = (8192 + n_batches - 1) / n_batches;
+    groups = groups < 1 ? 1 : (groups > n_iter ? n_iter : groups);
+    if (groups > 65535) groups = 65535;
+    dim3 grid((unsigned)n_batches, (unsigned)groups);
     hipLaunchKernelGGL((k_accumulate<VT, B, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
                        slot_q, n_slots, n_sample, maxima, theta, count, cand, cap);
     return hipGetLastError();
@@ -730,12 +900,13 @@ hipError_t dispatch_b(int batch, const DevIndex &ix, const DevQueries &q, const 
 }  // namespace
 
 hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, DevCoarse c,
-                             double *scratch_abs, int32_t *err_flag, hipStream_t s)
+                             const float *term_max, double *scratch_abs, int32_t *err_flag,
+                             hipStream_t s)
 {
     if (q.n_rows == 0) return hipSuccess;
     dim3 grid((unsigned)((q.n_rows + 3) / 4));
-    hipLaunchKernelGGL(k_query_prep, grid, dim3(256), 0, s, q, n_cols, beta, c, scratch_abs,
-                       err_flag);
+    hipLaunchKernelGGL(k_query_prep, grid, dim3(256), 0, s, q, n_cols, beta, c, term_max,
+                       scratch_abs, err_flag);
     return hipGetLastError();
 }
 
