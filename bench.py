@@ -62,7 +62,20 @@ def main():
     ap.add_argument("--recall-queries", type=int, default=128)
     ap.add_argument("--oracle-queries", type=int, default=256)
     ap.add_argument("--no-oracle", action="store_true", help="skip recall and the CPU baseline")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index is not "
@@ -127,7 +140,7 @@ def main():
     del ex_off
     vbytes = {"f32": 4, "f16": 2, "bf16": 2}[dtype]
     bpp = 2 + vbytes
-    batch = args.batch or 4
+    batch = args.batch or 1
     union_post = batch_union_postings(queries, term_len, batch)
     query_post = per_query_postings(queries, term_len)
     offs_bytes = int(queries.nnz) * int(info["n_tiles"]) * 8

@@ -145,8 +145,8 @@ hipError_t timed(int cat, hipStream_t s, F fn)
     return e;
 }
 
-constexpr int32_t kDefaultTile = 4096;
-constexpr int32_t kDefaultBatch = 4;
+constexpr int32_t kDefaultTile = 8192;
+constexpr int32_t kDefaultBatch = 1;
 constexpr int32_t kDefaultCandCap = 32768;
 constexpr int32_t kDefaultSampleTiles = 32;
 constexpr int32_t kDefaultGamma = 500;

@@ -48,11 +48,11 @@ struct DevCoarse {
     float *qinv;
 };
 
-constexpr int kAccThreads = 1024;      // accumulate kernel workgroup
+constexpr int kAccThreads = 512;       // accumulate kernel workgroup
 constexpr int kFinThreads = 256;       // finalize / theta kernels
 constexpr int kGammaMax = 4096;        // largest reorder pool
 constexpr int kQueryHash = 8192;       // rerank hash slots (query nnz <= kQueryHash / 2)
-constexpr int kEntryBlock = 1024;      // (query, term) entries merged per pass in the accumulate kernel
+constexpr int kEntryBlock = 512;       // (query, term) entries merged per pass in the accumulate kernel
 constexpr int kUnroll = 4;             // 4-posting groups in flight per lane
 
 // LDS of one accumulate workgroup: the score rows A[batch][tile_stride], the

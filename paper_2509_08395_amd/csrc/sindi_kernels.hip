@@ -336,23 +336,65 @@ template <> struct Weights<2> {
     }
 };
 
+// Emit the scores of one query row segment that reach the threshold: each
+// lane holds NV scores of consecutive documents starting at m0.
+template <int NV>
+__device__ __forceinline__ void emit_candidates(const float (&sv)[NV], const bool (&ok)[NV],
+                                                int64_t doc0, uint32_t *cnt, uint64_t *out,
+                                                int64_t cap)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t bal[NV];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int p = 0; p < NV; ++p) {
+        bal[p] = __ballot(ok[p]);
+        tot += (uint32_t)__popcll(bal[p]);
+    }
+    uint32_t b0 = 0;
+    if (lane == 0) b0 = atomicAdd(cnt, tot);
+    b0 = __shfl(b0, 0, kWave);
+#pragma unroll
+    for (int p = 0; p < NV; ++p) {
+        if (ok[p]) {
+            const uint64_t pos = (uint64_t)b0 + lanes_below(bal[p]);
+            if (pos < (uint64_t)cap) out[pos] = make_key(sv[p], (uint32_t)(doc0 + p));
+        }
+        b0 += (uint32_t)__popcll(bal[p]);
+    }
+}
+
+// Decode a pair-packed 64-bit score word into the two 32-bit sums it holds:
+// the word is H * 2^32 + L (exactly, modulo 2^64) with |L|, |H| < 2^31.
+__device__ __forceinline__ void unpack_pair(uint32_t wlo, uint32_t whi, int32_t &l, int32_t &h)
+{
+    l = (int32_t)wlo;
+    h = (int32_t)(whi + (l < 0 ? 1u : 0u));
+}
+
 // One workgroup = a batch of B query slots x a strided set of tiles.  The
 // batch's (query, term) entries are first merged into one ascending list of
 // distinct terms, each with a weight per query (zero where the query lacks
 // the term), so a list I_{term, tile} shared by several queries of the batch
-// is read once.  Then, for every tile: the score rows A[b][0..len) (the
-// window's distance array of Sec. 3.3.1, one row per query) are cleared in
-// LDS; the tile's lists of all merged terms are laid end to end as aligned
-// 4-posting groups and the waves sweep that range, kUnroll groups per lane in
-// flight; every posting adds w_b * x to A[b][doc] for each query b holding
-// the term (Alg. 2: product, then accumulate).  Different terms can hit one
-// document concurrently, so the adds are LDS atomics, on 32-bit integers:
-// each product is rounded once to the query's fixed-point grid (weights
-// arrive pre-scaled), which makes the sums exact, independent of the order
-// of the atomics, and several times faster than float LDS atomics on this
-// chip.  Scores are converted back to FP32 when read.  Finally the rows are
-// either sampled (per-thread maxima, for the candidate threshold) or every
-// score at or above the query's threshold is appended to its candidate list.
+// is read once.  Then, for every tile: the score rows (the window's distance
+// array of Sec. 3.3.1, one per query) are cleared in LDS; the tile's lists of
+// all merged terms are laid end to end as aligned 4-posting groups, and each
+// wave sweeps one contiguous share of that range, kUnroll groups per lane in
+// flight; every posting adds w_b * x to query b's score of its document
+// (Alg. 2: product, then accumulate).
+//
+// Scores are 32-bit fixed point: weights arrive multiplied by the query's
+// power-of-two scale and each product is truncated once to an integer, so
+// the sums are exact and independent of the order of the adds; different
+// terms can hit one document concurrently, so the adds are LDS atomics, and
+// integer LDS atomics run many times faster than float ones on this chip.
+// For B >= 2 the rows of queries 2q and 2q+1 are interleaved into one 64-bit
+// word per document holding H * 2^32 + L, so one 64-bit atomic updates both
+// (the sums stay within +-2^30, so both halves decode exactly).
+//
+// Finally each row is either sampled (per-thread maxima, for the candidate
+// threshold) or every score at or above the query's threshold is appended to
+// its candidate list.
 template <int VT, int B, bool SAMPLE>
 __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
@@ -360,11 +402,14 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     int64_t cap)
 {
     constexpr int NT = kAccThreads, NW = NT / kWave, EB = kEntryBlock;
+    constexpr bool PACK = B >= 2;
+    constexpr int NP = PACK ? B / 2 : 1;  // score words per document
     static_assert(EB == NT, "one merged entry per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = ix.tile_stride;
-    int32_t *A = reinterpret_cast<int32_t *>(smem);  // fixed-point scores
-    int32_t *u_term = A + (size_t)B * T;
+    // PACK: uint64 [NP][T]; else int32 [T].  Both are B * T * 4 bytes.
+    unsigned char *A = smem;
+    int32_t *u_term = reinterpret_cast<int32_t *>(smem + (size_t)B * T * 4);
     float *u_w = reinterpret_cast<float *>(u_term + EB);  // [EB][B]
     unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (size_t)EB * B);
     uint64_t *keys = reinterpret_cast<uint64_t *>(region);                 // merge phase
@@ -378,6 +423,7 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     __shared__ float s_qinv[B];
     __shared__ uint32_t s_wsum[NW];
     __shared__ int32_t s_nu;
+    __shared__ uint64_t s_dummy[2];  // target of adds for masked-off postings
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int32_t batch = blockIdx.x;
@@ -460,7 +506,13 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
 
     if (n_blocks == 1) merge(0);
     const int64_t n_tile_iter = SAMPLE ? n_sample : ix.n_tiles;
+    constexpr int STEP = kWave * kUnroll;
+    using Raw = typename Val<VT>::Raw;
 
+    // With one merged block, each thread prefetches its term's list bounds of
+    // the next tile while the current tile accumulates.
+    uint32_t pre_lo = 0, pre_hi = 0;
+    bool have_pre = false;
     for (int64_t ti = blockIdx.y; ti < n_tile_iter; ti += gridDim.y) {
         const int64_t t = SAMPLE ? (ti * ix.n_tiles / n_sample) : ti;
         const int64_t d0 = ix.tile_doc[t];
@@ -480,7 +532,8 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
             uint32_t ng = 0, gs = 0, hl = 0;
             if (tid < nu) {
                 const int32_t term = u_term[tid];
-                const uint32_t lo = toff[term], hi = toff[term + 1];
+                const uint32_t lo = have_pre ? pre_lo : toff[term];
+                const uint32_t hi = have_pre ? pre_hi : toff[term + 1];
                 if (hi > lo) {
                     const uint64_t a = P0 + lo;
                     gs = (uint32_t)(a >> 2);
@@ -498,114 +551,167 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
             }
             gp[tid] = ex;
             if (tid == 0) gp[nu] = total;
+            have_pre = false;
+            if (n_blocks == 1) {
+                const int64_t tn = ti + gridDim.y;
+                if (tn < n_tile_iter) {
+                    have_pre = true;
+                    if (tid < nu) {
+                        const int64_t t2 = SAMPLE ? (tn * ix.n_tiles / n_sample) : tn;
+                        const uint32_t *toff2 = ix.term_off + (size_t)t2 * (size_t)(ix.n_cols + 1);
+                        const int32_t term = u_term[tid];
+                        pre_lo = toff2[term];
+                        pre_hi = toff2[term + 1];
+                    }
+                }
+            }
             __syncthreads();
 
-            constexpr int STEP = kWave * kUnroll;
-            using Raw = typename Val<VT>::Raw;
-            for (uint32_t base = (uint32_t)wave * STEP; base < total; base += (uint32_t)NW * STEP) {
-                const uint32_t last = min(base + (uint32_t)STEP, total) - 1u;
-                int u0, u1;
-                {  // entries holding the first and the last group of this step
-                    int l = 0, h = nu - 1;
-                    while (l < h) {
-                        const int m = (l + h + 1) >> 1;
-                        if (gp[m] <= base) l = m; else h = m - 1;
-                    }
-                    u0 = l;
-                    h = nu - 1;
-                    while (l < h) {
-                        const int m = (l + h + 1) >> 1;
-                        if (gp[m] <= last) l = m; else h = m - 1;
-                    }
-                    u1 = l;
+            // this wave's contiguous share of the groups, in whole steps
+            const uint32_t share = ((total + NW - 1) / NW + STEP - 1) / STEP * STEP;
+            const uint32_t g_beg = min(total, (uint32_t)wave * share);
+            const uint32_t g_end = min(total, g_beg + share);
+            int ub = 0;
+            if (g_beg < g_end) {
+                int l = 0, h = nu - 1;
+                while (l < h) {
+                    const int m = (l + h + 1) >> 1;
+                    if (gp[m] <= g_beg) l = m; else h = m - 1;
                 }
+                ub = l;
+            }
+            for (uint32_t base = g_beg; base < g_end; base += STEP) {
+                while (gp[ub + 1] <= base) ++ub;  // wave-uniform
                 uint2 ids[kUnroll];
                 Raw raw[kUnroll];
                 int uu[kUnroll];
                 uint32_t jj[kUnroll];
+                int u = ub;
 #pragma unroll
                 for (int i = 0; i < kUnroll; ++i) {
                     const uint32_t vg = base + (uint32_t)(i * kWave + lane);
                     uu[i] = -1;
-                    if (vg < total) {
-                        int l = u0, h = u1;
-                        while (l < h) {
-                            const int m = (l + h + 1) >> 1;
-                            if (gp[m] <= vg) l = m; else h = m - 1;
-                        }
-                        uu[i] = l;
-                        jj[i] = vg - gp[l];
-                        const uint64_t g = (uint64_t)u_gs[l] + jj[i];
+                    if (vg < g_end) {
+                        while (gp[u + 1] <= vg) ++u;
+                        uu[i] = u;
+                        jj[i] = vg - gp[u];
+                        const uint64_t g = (uint64_t)u_gs[u] + jj[i];
                         ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g];
                         raw[i] = Val<VT>::load(ix.post_val, g);
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < kUnroll; ++i) {
-                    const int u = uu[i];
-                    if (u < 0) continue;
-                    const uint32_t hl = u_hl[u];
-                    const uint32_t lr = hl >> 30, hr = hl & 0x3FFFFFFFu, r0 = 4u * jj[i];
+                    const int uw = uu[i];
+                    if (uw < 0) continue;
+                    const uint32_t hl2 = u_hl[uw];
+                    const uint32_t lr = hl2 >> 30, hr = hl2 & 0x3FFFFFFFu, r0 = 4u * jj[i];
                     float w[B];
-                    Weights<B>::read(u_w + (size_t)u * B, w);
+                    Weights<B>::read(u_w + (size_t)uw * B, w);
                     float v[4];
                     Val<VT>::decode(raw[i], v);
                     const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16, ids[i].y & 0xFFFFu,
                                             ids[i].y >> 16};
+                    bool ok[4];
 #pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-                        if (r0 + p < lr || r0 + p >= hr) continue;
+                    for (int p = 0; p < 4; ++p) ok[p] = r0 + p >= lr && r0 + p < hr;
+                    if (PACK) {
+                        uint64_t *A64 = reinterpret_cast<uint64_t *>(A);
 #pragma unroll
-                        for (int b = 0; b < B; ++b)
-                            if (w[b] != 0.0f)
-                                lds_add_i32(&A[(size_t)b * T + d4[p]], __float2int_rn(w[b] * v[p]));
+                        for (int qp = 0; qp < NP; ++qp) {
+                            const float w0 = w[2 * qp], w1 = w[2 * qp + 1];
+                            if (w0 == 0.0f && w1 == 0.0f) continue;
+#pragma unroll
+                            for (int p = 0; p < 4; ++p) {
+                                const int32_t lo = (int32_t)(w0 * v[p]);
+                                const int32_t hi = (int32_t)(w1 * v[p]);
+                                const uint32_t hw = (uint32_t)hi + (uint32_t)(lo >> 31);
+                                uint64_t add = ((uint64_t)hw << 32) | (uint32_t)lo;
+                                uint64_t *dst = A64 + (size_t)qp * T + d4[p];
+                                dst = ok[p] ? dst : s_dummy;
+                                add = ok[p] ? add : 0ull;
+                                __hip_atomic_fetch_add(dst, add, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
+                        }
+                    } else {
+                        int32_t *A32 = reinterpret_cast<int32_t *>(A);
+#pragma unroll
+                        for (int p = 0; p < 4; ++p) {
+                            int32_t *dst = ok[p] ? A32 + d4[p] : reinterpret_cast<int32_t *>(s_dummy);
+                            lds_add_i32(dst, ok[p] ? (int32_t)(w[0] * v[p]) : 0);
+                        }
                     }
                 }
             }
             __syncthreads();
         }
 
-        for (int b = 0; b < B; ++b) {
-            const int32_t slot = s_slot[b];
-            if (slot < 0) continue;
-            const int32_t *Ar = A + (size_t)b * T;
-            const float qinv = s_qinv[b];
-            if (SAMPLE) {
-                int32_t mx = INT32_MIN;
-                for (int m = tid; m < len; m += NT) mx = max(mx, Ar[m]);
-                maxima[((size_t)slot * n_sample + ti) * NT + tid] =
-                    tid < len ? (float)mx * qinv : -INFINITY;
-            } else {
-                const float th = theta[slot];
-                uint32_t *cnt = count + slot;
-                uint64_t *out = cand + (size_t)slot * (size_t)cap;
-                for (int base = wave * 256; base < len; base += NW * 256) {
-                    const int m0 = base + lane * 4;
-                    int4 s4 = make_int4(0, 0, 0, 0);
-                    if (m0 < len) s4 = *reinterpret_cast<const int4 *>(Ar + m0);
-                    const float sv[4] = {(float)s4.x * qinv, (float)s4.y * qinv,
-                                         (float)s4.z * qinv, (float)s4.w * qinv};
-                    bool pr[4];
-                    uint64_t bal[4];
-                    uint32_t tot = 0;
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-                        pr[p] = (m0 + p < len) && sv[p] >= th;
-                        bal[p] = __ballot(pr[p]);
-                        tot += (uint32_t)__popcll(bal[p]);
+        // ---- read the rows: sample maxima or emit candidates
+        if (PACK) {
+            const uint64_t *A64 = reinterpret_cast<const uint64_t *>(A);
+            for (int qp = 0; qp < NP; ++qp) {
+                const int32_t sl0 = s_slot[2 * qp], sl1 = s_slot[2 * qp + 1];
+                if (sl0 < 0 && sl1 < 0) continue;
+                const float qi0 = s_qinv[2 * qp], qi1 = s_qinv[2 * qp + 1];
+                const uint64_t *row = A64 + (size_t)qp * T;
+                if (SAMPLE) {
+                    int32_t m0 = INT32_MIN, m1 = INT32_MIN;
+                    for (int m = tid; m < len; m += NT) {
+                        const uint64_t wd = row[m];
+                        int32_t l, h;
+                        unpack_pair((uint32_t)wd, (uint32_t)(wd >> 32), l, h);
+                        m0 = max(m0, l);
+                        m1 = max(m1, h);
                     }
-                    if (tot == 0) continue;
-                    uint32_t b0 = 0;
-                    if (lane == 0) b0 = atomicAdd(cnt, tot);
-                    b0 = __shfl(b0, 0, kWave);
+                    if (sl0 >= 0)
+                        maxima[((size_t)sl0 * n_sample + ti) * NT + tid] = tid < len ? (float)m0 * qi0 : -INFINITY;
+                    if (sl1 >= 0)
+                        maxima[((size_t)sl1 * n_sample + ti) * NT + tid] = tid < len ? (float)m1 * qi1 : -INFINITY;
+                } else {
+                    const float th0 = sl0 >= 0 ? theta[sl0] : INFINITY;
+                    const float th1 = sl1 >= 0 ? theta[sl1] : INFINITY;
+                    for (int base = wave * 128; base < len; base += NW * 128) {
+                        const int m0 = base + lane * 2;
+                        int4 r = make_int4(0, 0, 0, 0);
+                        if (m0 < len) r = *reinterpret_cast<const int4 *>(row + m0);
+                        int32_t l0, h0, l1, h1;
+                        unpack_pair((uint32_t)r.x, (uint32_t)r.y, l0, h0);
+                        unpack_pair((uint32_t)r.z, (uint32_t)r.w, l1, h1);
+                        const float a[2] = {(float)l0 * qi0, (float)l1 * qi0};
+                        const float b2[2] = {(float)h0 * qi1, (float)h1 * qi1};
+                        const bool oa[2] = {m0 < len && a[0] >= th0, m0 + 1 < len && a[1] >= th0};
+                        const bool ob[2] = {m0 < len && b2[0] >= th1, m0 + 1 < len && b2[1] >= th1};
+                        if (__ballot(oa[0] || oa[1] || ob[0] || ob[1]) == 0) continue;
+                        if (sl0 >= 0)
+                            emit_candidates<2>(a, oa, d0 + m0, count + sl0, cand + (size_t)sl0 * cap, cap);
+                        if (sl1 >= 0)
+                            emit_candidates<2>(b2, ob, d0 + m0, count + sl1, cand + (size_t)sl1 * cap, cap);
+                    }
+                }
+            }
+        } else {
+            const int32_t *A32 = reinterpret_cast<const int32_t *>(A);
+            const int32_t slot = s_slot[0];
+            if (slot >= 0) {
+                const float qinv = s_qinv[0];
+                if (SAMPLE) {
+                    int32_t mx = INT32_MIN;
+                    for (int m = tid; m < len; m += NT) mx = max(mx, A32[m]);
+                    maxima[((size_t)slot * n_sample + ti) * NT + tid] = tid < len ? (float)mx * qinv : -INFINITY;
+                } else {
+                    const float th = theta[slot];
+                    for (int base = wave * 256; base < len; base += NW * 256) {
+                        const int m0 = base + lane * 4;
+                        int4 r = make_int4(0, 0, 0, 0);
+                        if (m0 < len) r = *reinterpret_cast<const int4 *>(A32 + m0);
+                        const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv,
+                                             (float)r.z * qinv, (float)r.w * qinv};
+                        bool ok[4];
 #pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-                        if (pr[p]) {
-                            const uint64_t pos = (uint64_t)b0 + lanes_below(bal[p]);
-                            if (pos < (uint64_t)cap)
-                                out[pos] = make_key(sv[p], (uint32_t)(d0 + m0 + p));
-                        }
-                        b0 += (uint32_t)__popcll(bal[p]);
+                        for (int p = 0; p < 4; ++p) ok[p] = (m0 + p < len) && sv[p] >= th;
+                        if (__ballot(ok[0] || ok[1] || ok[2] || ok[3]) == 0) continue;
+                        emit_candidates<4>(sv, ok, d0 + m0, count + slot, cand + (size_t)slot * cap, cap);
                     }
                 }
             }
