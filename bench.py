@@ -46,6 +46,27 @@ def per_query_postings(qc, term_len):
     return int(term_len[qc.indices].sum())
 
 
+def measured_traffic(config):
+    """HBM bytes per scoring launch from the committed rocprofv3 counter summary, if it was
+    taken on this exact kernel source and configuration; else None."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2509_08395_amd", "csrc", "sindi_kernels.hip")
+    path = os.path.join(ROOT, "profiles", f"k_accumulate_{config['workload']}_{config['value_storage']}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    "):
+            key, val = line.strip().split(":", 1)
+            fields[key.strip()] = val.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    want = (f"batch={config['batch']} tile={config['tile']} value_storage={config['value_storage']} "
+            f"n_queries={config['n_queries']} n_docs={config['n_docs']}")
+    if fields.get("kernel_source_sha256") != sha or fields.get("config") != want:
+        return None
+    return int(fields["fetch_bytes_per_launch"]) + int(fields["write_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,7 +81,7 @@ def main():
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--gamma", type=int, default=0)
     ap.add_argument("--recall-queries", type=int, default=128)
-    ap.add_argument("--oracle-queries", type=int, default=256)
+    ap.add_argument("--oracle-queries", type=int, default=7000)
     ap.add_argument("--no-oracle", action="store_true", help="skip recall and the CPU baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (reference for HBM byte counters)")
@@ -170,6 +191,7 @@ def main():
         "build_s": round(build_s, 2),
         "roofline": roofline,
     }
+    roofline["traffic"] = measured_traffic(result["config"])
 
     if not args.no_oracle:
         import oracle  # CPU baseline and recall only
