@@ -77,6 +77,7 @@ typedef struct {
     int32_t cand_cap;        /* per-query candidate buffer entries; 0 -> library default     */
     int32_t sample_tiles;    /* tiles scored first to set each query's candidate threshold;
                                 0 -> library default, -1 -> no threshold (keep every doc)    */
+    int32_t tile_run;        /* consecutive tiles swept by one workgroup; 0 -> default       */
 } sindi_search_params;
 
 /* Summary of a built index. */

@@ -151,7 +151,8 @@ class Index:
                 "term_off": term_off.reshape(nt, nc + 1), "post_doc": post_doc[:npost],
                 "post_val": post_val.view(vt)[:npost]}
 
-    def _run(self, fn, queries, k, beta, gamma, batch, cand_cap, sample_tiles, stream, out):
+    def _run(self, fn, queries, k, beta, gamma, batch, cand_cap, sample_tiles, stream, out,
+             tile_run=0):
         import torch
         qs, keep = _query_struct(queries)
         nq = qs.n_rows
@@ -161,7 +162,7 @@ class Index:
         else:
             ids, scores = out
         params = _lib.SindiSearchParams(float(beta), int(gamma), int(batch), int(cand_cap),
-                                        int(sample_tiles))
+                                        int(sample_tiles), int(tile_run))
         _lib.check(fn(self._h, ctypes.byref(qs), int(k), ctypes.byref(params),
                       ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(scores.data_ptr()),
                       _stream(stream)))
@@ -169,16 +170,16 @@ class Index:
         return ids, scores
 
     def search(self, queries, k, beta=1.0, gamma=0, batch=0, cand_cap=0, sample_tiles=0,
-               stream=None, out=None):
+               stream=None, out=None, tile_run=0):
         """Alg. 4: (ids int64 [n, k], scores float32 [n, k]) as CUDA tensors."""
         return self._run(_lib.load().sindi_search, queries, k, beta, gamma, batch, cand_cap,
-                         sample_tiles, stream, out)
+                         sample_tiles, stream, out, tile_run)
 
     def search_coarse(self, queries, k, beta=1.0, batch=0, cand_cap=0, sample_tiles=0,
-                      stream=None, out=None):
+                      stream=None, out=None, tile_run=0):
         """Alg. 2 over the (pruned) index: coarse top-k, no rerank."""
         return self._run(_lib.load().sindi_search_coarse, queries, k, beta, 0, batch, cand_cap,
-                         sample_tiles, stream, out)
+                         sample_tiles, stream, out, tile_run)
 
     def score(self, queries: DeviceCsr, cand, stream=None):
         """delta(q_b, x_c) for cand [n_q, n_cand] (int64 CUDA) -> float32 [n_q, n_cand]."""

@@ -1,6 +1,7 @@
 // Host side of the SINDI library: input validation, mass-ratio pruning,
 // window/tile layout of the inverted lists, device upload, and the search
-// pipeline that drives the gfx950 kernels.  Implements include/sindi.h.
+// pipeline that drives the gfx950 kernels.  Implements include/sindi.h
+// (the serving loop is in sindi_server.cpp).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,12 +20,14 @@
 
 #include "sindi.h"
 #include "sindi_internal.h"
+#include "sindi_state.h"
 
-using namespace sindi;
+namespace sindi {
 
 // ------------------------------------------------------------------ errors
 namespace {
 thread_local std::string g_err;
+}
 
 sindi_status fail(sindi_status st, const char *fmt, ...)
 {
@@ -37,11 +40,7 @@ sindi_status fail(sindi_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIP_TRY(expr)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess) return fail(SINDI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+const char *last_error() { return g_err.c_str(); }
 
 int host_threads()
 {
@@ -51,65 +50,8 @@ int host_threads()
     return n < 1 ? 1 : (n > 64 ? 64 : n);
 }
 
-// Run fn(lo, hi) over [0, n) in contiguous slices on the host threads.
-template <typename F>
-void parallel_for(int64_t n, F fn)
-{
-    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(n / 1024, 1));
-    if (nt <= 1) {
-        fn((int64_t)0, n);
-        return;
-    }
-    std::vector<std::thread> th;
-    const int64_t step = (n + nt - 1) / nt;
-    for (int i = 0; i < nt; ++i) {
-        const int64_t lo = i * step, hi = std::min(n, lo + step);
-        if (lo >= hi) break;
-        th.emplace_back([=] { fn(lo, hi); });
-    }
-    for (auto &t : th) t.join();
-}
-
-// Grow-only device buffer.
-struct DBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    DBuf() = default;
-    DBuf(const DBuf &) = delete;
-    DBuf &operator=(const DBuf &) = delete;
-    ~DBuf() { release(); }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    hipError_t ensure(size_t n)
-    {
-        if (n <= bytes && p) return hipSuccess;
-        release();
-        size_t want = n < 256 ? 256 : n;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return e;
-        }
-        bytes = want;
-        return hipSuccess;
-    }
-    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
-};
-
-// FP32 -> FP16 / BF16, round to nearest even.
-uint16_t to_f16(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
-uint16_t to_bf16(float x)
-{
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 // ------------------------------------------------------------------ profiling
+namespace {
 struct Profiler {
     std::mutex mu;
     std::atomic<bool> on{false};
@@ -122,14 +64,11 @@ struct Profiler {
     double ms[5] = {0, 0, 0, 0, 0};
 };
 Profiler g_prof;
+}  // namespace
 
-enum { kProfPrep = 0, kProfSample = 1, kProfScore = 2, kProfTheta = 3, kProfFinal = 4 };
-
-// Launch through `fn`, bracketed by events on `s` while profiling is on.
-template <typename F>
-hipError_t timed(int cat, hipStream_t s, F fn)
+hipError_t timed_launch(int cat, hipStream_t s, hipError_t (*fn)(void *), void *ctx)
 {
-    if (!g_prof.on.load(std::memory_order_relaxed)) return fn();
+    if (!g_prof.on.load(std::memory_order_relaxed)) return fn(ctx);
     hipEvent_t a, b;
     hipError_t e = hipEventCreate(&a);
     if (e != hipSuccess) return e;
@@ -137,12 +76,58 @@ hipError_t timed(int cat, hipStream_t s, F fn)
     if (e != hipSuccess) return e;
     e = hipEventRecord(a, s);
     if (e != hipSuccess) return e;
-    e = fn();
+    e = fn(ctx);
     if (e != hipSuccess) return e;
     e = hipEventRecord(b, s);
     std::lock_guard<std::mutex> lock(g_prof.mu);
     g_prof.pending.push_back({cat, a, b});
     return e;
+}
+
+sindi_status profile_enable(int32_t enable)
+{
+    g_prof.on.store(enable != 0);
+    return SINDI_OK;
+}
+
+sindi_status profile_read(sindi_profile *out, int32_t reset)
+{
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    sindi_status st = SINDI_OK;
+    for (auto &r : g_prof.pending) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && st == SINDI_OK)
+            st = fail(SINDI_E_HIP, "sindi_profile_read: %s", hipGetErrorString(e));
+        g_prof.n[r.cat] += 1;
+        g_prof.ms[r.cat] += ms;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.pending.clear();
+    if (out)
+        for (int i = 0; i < 5; ++i) {
+            out->launches[i] = g_prof.n[i];
+            out->ms[i] = g_prof.ms[i];
+        }
+    if (reset)
+        for (int i = 0; i < 5; ++i) {
+            g_prof.n[i] = 0;
+            g_prof.ms[i] = 0.0;
+        }
+    return st;
+}
+
+namespace {
+
+// FP32 -> FP16 / BF16, round to nearest even.
+uint16_t to_f16(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+uint16_t to_bf16(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
 }
 
 constexpr int32_t kDefaultTile = 8192;
@@ -153,49 +138,6 @@ constexpr int32_t kDefaultGamma = 500;
 constexpr size_t kCandBudget = size_t(2) << 30;  // candidate buffer bytes per pass
 
 }  // namespace
-
-// ------------------------------------------------------------------ index
-struct sindi_index {
-    int64_t n_docs = 0, n_cols = 0, nnz = 0, n_post = 0, window = 0, n_windows = 0, n_tiles = 0;
-    int32_t tile_max = 0, tile_stride = 0, dtype = 0;
-    double alpha = 1.0;
-    int device = 0;
-    int64_t max_lds = 0;
-    std::vector<int64_t> h_tile_doc;
-    DBuf indptr, indices, values, tile_doc, tile_post, term_off, post_doc, post_val, term_max;
-    // search workspace, guarded by mu
-    std::mutex mu;
-    DBuf q_ptr, q_idx, q_val, ct, cw, cn, qinv, sabs, err, status, slot_q, maxima, theta, count, cand;
-
-    DevIndex dev() const
-    {
-        DevIndex d;
-        d.n_docs = n_docs;
-        d.n_cols = n_cols;
-        d.n_tiles = n_tiles;
-        d.tile_stride = tile_stride;
-        d.value_dtype = dtype;
-        d.tile_doc = tile_doc.as<int64_t>();
-        d.tile_post = tile_post.as<int64_t>();
-        d.term_off = term_off.as<uint32_t>();
-        d.post_doc = post_doc.as<uint16_t>();
-        d.post_val = post_val.p;
-        d.term_max = term_max.as<float>();
-        d.indptr = indptr.as<int64_t>();
-        d.indices = indices.as<int32_t>();
-        d.values = values.as<float>();
-        d.nnz = nnz;
-        return d;
-    }
-    int64_t device_bytes() const
-    {
-        return (int64_t)(indptr.bytes + indices.bytes + values.bytes + tile_doc.bytes +
-                         tile_post.bytes + term_off.bytes + post_doc.bytes + post_val.bytes +
-                         term_max.bytes);
-    }
-};
-
-namespace {
 
 // Structural check of a host CSR (Def. 1: each row a set of non-zero
 // entries over [0, n_cols); ids strictly ascending; finite values).
@@ -238,6 +180,8 @@ sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max
     }
     return SINDI_OK;
 }
+
+namespace {
 
 // Def. 6 for one row: keep[e] = 1 for the entries of the alpha-mass
 // subvector.  Entries ranked by |x| descending, equal |x| by ascending term
@@ -373,6 +317,8 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     if (range_bad) return fail(SINDI_E_RANGE, "sindi_build: a kept value overflows the storage type");
     for (int64_t t = 0; t < n_tiles; ++t) tile_post[t + 1] += tile_post[t];
     const int64_t n_post = tile_post[n_tiles];
+    if (n_post >= ((int64_t)1 << 33))
+        return fail(SINDI_E_INVALID, "sindi_build: more than 2^33 index postings");
     ix->n_post = n_post;
     const int64_t n_pad = (n_post + 3) / 4 * 4 + 8;
     const size_t vbytes = p->value_dtype == SINDI_F32 ? 4 : 2;
@@ -446,14 +392,169 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     return SINDI_OK;
 }
 
+
+}  // namespace
+
 // ------------------------------------------------------------------ search
-int pick_batch(const sindi_index *ix, int32_t req)
+sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
+                       const sindi_search_params &p, bool rerank, const char *fn, Plan &pl)
 {
-    int b = req ? req : kDefaultBatch;
-    if (b != 1 && b != 2 && b != 4 && b != 8) return -1;
+    pl = Plan{};
+    pl.rerank = rerank;
+    pl.k = k;
+    pl.beta = p.beta == 0.0 ? 1.0 : p.beta;
+    if (!(pl.beta > 0.0 && pl.beta <= 1.0))
+        return fail(SINDI_E_INVALID, "%s: beta must be in (0, 1]", fn);
+    if (k < 1 || k > kGammaMax) return fail(SINDI_E_INVALID, "%s: k must be in [1, %d]", fn, kGammaMax);
+    pl.gamma = rerank ? (p.gamma ? p.gamma : std::max(k, kDefaultGamma)) : k;
+    if (pl.gamma < k || pl.gamma > kGammaMax)
+        return fail(SINDI_E_INVALID, "%s: gamma must be in [k, %d]", fn, kGammaMax);
+    int b = p.batch ? p.batch : kDefaultBatch;
+    if (b != 1 && b != 2 && b != 4 && b != 8)
+        return fail(SINDI_E_INVALID, "%s: batch must be 1, 2, 4 or 8", fn);
     while (b > 1 && (int64_t)accumulate_lds_bytes(b, ix->tile_stride) > ix->max_lds) b >>= 1;
-    return b;
+    pl.batch = b;
+    pl.tile_run = p.tile_run;
+    pl.need = (int32_t)std::min<int64_t>(pl.gamma, std::max<int64_t>(ix->n_docs, 1));
+    // candidate threshold: sample tiles first, or keep every document
+    int64_t cap = p.cand_cap > 0 ? p.cand_cap : kDefaultCandCap;
+    cap = std::max<int64_t>(cap, pl.need);
+    pl.keep_all = p.sample_tiles < 0 || ix->n_docs <= cap;
+    if (pl.keep_all) cap = std::max<int64_t>(ix->n_docs, 1);
+    pl.cap = cap;
+    pl.n_sample = pl.keep_all ? 0
+                              : (int32_t)std::min<int64_t>(
+                                    ix->n_tiles, p.sample_tiles ? p.sample_tiles : kDefaultSampleTiles);
+    if (!pl.keep_all) {
+        int64_t sampled = 0;
+        const std::vector<int64_t> &td = ix->h_tile_doc;
+        for (int64_t i = 0; i < pl.n_sample; ++i) {
+            const int64_t t = i * ix->n_tiles / pl.n_sample;
+            sampled += td[t + 1] - td[t];
+        }
+        const double f = (double)sampled / (double)ix->n_docs;
+        pl.n_max = (int64_t)pl.n_sample * kAccThreads;
+        pl.rank = std::min<int64_t>(pl.n_max, (int64_t)std::ceil(2.0 * pl.need * f) + 8);
+    }
+    pl.group = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(kCandBudget / plan_query_bytes(pl))));
+    return SINDI_OK;
 }
+
+sindi_status reserve_workspace(Workspace &ws, const Plan &pl, int64_t nq, int64_t nnz)
+{
+    HIP_TRY(ws.ct.ensure((size_t)nnz * 4 + 4));
+    HIP_TRY(ws.cw.ensure((size_t)nnz * 4 + 4));
+    HIP_TRY(ws.cn.ensure((size_t)nq * 4 + 4));
+    HIP_TRY(ws.qinv.ensure((size_t)nq * 4 + 4));
+    HIP_TRY(ws.sabs.ensure(pl.beta < 1.0 ? (size_t)nnz * 8 + 8 : 8));
+    HIP_TRY(ws.err.ensure(4));
+    HIP_TRY(ws.status.ensure((size_t)nq * 4 + 4));
+    const int64_t g = std::min<int64_t>(pl.group, std::max<int64_t>(nq, 1));
+    HIP_TRY(ws.cand.ensure((size_t)g * pl.cap * 8));
+    HIP_TRY(ws.count.ensure((size_t)g * 4));
+    HIP_TRY(ws.theta.ensure((size_t)g * 4));
+    HIP_TRY(ws.slot_q.ensure((size_t)g * 4));
+    if (!pl.keep_all) HIP_TRY(ws.maxima.ensure((size_t)g * pl.n_max * 4));
+    return SINDI_OK;
+}
+
+sindi_status enqueue_prep(const sindi_index *ix, Workspace &ws, const Plan &pl,
+                          const DevQueries &dq, hipStream_t s)
+{
+    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 1, 0u, s));
+    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
+    HIP_TRY(timed(kProfPrep, s, [&] {
+        return launch_query_prep(dq, ix->n_cols, pl.beta, dc, ix->term_max.as<float>(),
+                                 ws.sabs.as<double>(), ws.err.as<int32_t>(), s);
+    }));
+    return SINDI_OK;
+}
+
+sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl,
+                            const DevQueries &dq, int64_t *out_ids, float *out_scores,
+                            hipStream_t s)
+{
+    const int64_t nq = dq.n_rows;
+    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
+    if (ix->n_docs == 0) {
+        HIP_TRY(launch_fill_f32(out_scores, nq * pl.k, -INFINITY, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(out_ids), 2 * nq * pl.k, 0xFFFFFFFFu, s));
+        HIP_TRY(launch_fill_u32(ws.status.as<uint32_t>(), nq, (uint32_t)kSlotOk, s));
+        return SINDI_OK;
+    }
+    const DevIndex dix = ix->dev();
+    for (int64_t g0 = 0; g0 < nq; g0 += pl.group) {
+        const int32_t ns = (int32_t)std::min<int64_t>(pl.group, nq - g0);
+        HIP_TRY(launch_iota(ws.slot_q.as<int32_t>(), ns, (int32_t)g0, s));
+        if (pl.keep_all) {
+            HIP_TRY(launch_fill_f32(ws.theta.as<float>(), ns, -INFINITY, s));
+        } else {
+            HIP_TRY(timed(kProfSample, s, [&] {
+                return launch_accumulate(dix, dq, dc, pl.batch, true, ws.slot_q.as<int32_t>(), ns,
+                                         pl.n_sample, ws.maxima.as<float>(), nullptr, nullptr,
+                                         nullptr, 0, pl.tile_run, s);
+            }));
+            HIP_TRY(timed(kProfTheta, s, [&] {
+                return launch_theta(ws.maxima.as<float>(), pl.n_max, pl.rank, ns,
+                                    ws.theta.as<float>(), s);
+            }));
+        }
+        HIP_TRY(launch_fill_u32(ws.count.as<uint32_t>(), ns, 0u, s));
+        HIP_TRY(timed(kProfScore, s, [&] {
+            return launch_accumulate(dix, dq, dc, pl.batch, false, ws.slot_q.as<int32_t>(), ns, 0,
+                                     nullptr, ws.theta.as<float>(), ws.count.as<uint32_t>(),
+                                     ws.cand.as<uint64_t>(), pl.cap, pl.tile_run, s);
+        }));
+        HIP_TRY(timed(kProfFinal, s, [&] {
+            return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
+                                   ws.cand.as<uint64_t>(), pl.cap, pl.need, pl.k, pl.rerank,
+                                   out_ids, out_scores, ws.status.as<int32_t>(), s);
+        }));
+    }
+    return SINDI_OK;
+}
+
+sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
+                           const DevQueries &dq, const std::vector<int32_t> &rows,
+                           int64_t *out_ids, float *out_scores, hipStream_t s, const char *fn)
+{
+    if (rows.empty()) return SINDI_OK;
+    const DevIndex dix = ix->dev();
+    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
+    // threshold missed gamma candidates or overflowed: keep every document
+    const int64_t cap_all = ix->n_docs;
+    const int64_t g_all = std::max<int64_t>(1, (int64_t)(kCandBudget / ((size_t)cap_all * 8)));
+    const int64_t gsz = std::min<int64_t>(g_all, (int64_t)rows.size());
+    HIP_TRY(ws.cand.ensure((size_t)gsz * cap_all * 8));
+    HIP_TRY(ws.count.ensure((size_t)gsz * 4));
+    HIP_TRY(ws.theta.ensure((size_t)gsz * 4));
+    HIP_TRY(ws.slot_q.ensure((size_t)gsz * 4));
+    for (size_t g0 = 0; g0 < rows.size(); g0 += (size_t)gsz) {
+        const int32_t ns = (int32_t)std::min<size_t>((size_t)gsz, rows.size() - g0);
+        HIP_TRY(hipMemcpyAsync(ws.slot_q.p, rows.data() + g0, (size_t)ns * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_fill_f32(ws.theta.as<float>(), ns, -INFINITY, s));
+        HIP_TRY(launch_fill_u32(ws.count.as<uint32_t>(), ns, 0u, s));
+        HIP_TRY(timed(kProfScore, s, [&] {
+            return launch_accumulate(dix, dq, dc, 1, false, ws.slot_q.as<int32_t>(), ns, 0, nullptr,
+                                     ws.theta.as<float>(), ws.count.as<uint32_t>(),
+                                     ws.cand.as<uint64_t>(), cap_all, pl.tile_run, s);
+        }));
+        HIP_TRY(timed(kProfFinal, s, [&] {
+            return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
+                                   ws.cand.as<uint64_t>(), cap_all, pl.need, pl.k, pl.rerank,
+                                   out_ids, out_scores, ws.status.as<int32_t>(), s);
+        }));
+        HIP_TRY(hipStreamSynchronize(s));  // rows[] is pageable host memory
+    }
+    std::vector<int32_t> status((size_t)dq.n_rows);
+    HIP_TRY(hipMemcpyAsync(status.data(), ws.status.p, (size_t)dq.n_rows * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int32_t q : rows)
+        if (status[q] != kSlotOk) return fail(SINDI_E_INTERNAL, "%s: query %d unresolved", fn, q);
+    return SINDI_OK;
+}
+
+namespace {
 
 sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
                          const sindi_search_params *pp, int64_t *out_ids, float *out_scores,
@@ -462,167 +563,60 @@ sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
     if (!ix || !qc || !out_ids || !out_scores) return fail(SINDI_E_INVALID, "%s: null argument", fn);
     sindi_search_params p{};
     if (pp) p = *pp;
-    const double beta = p.beta == 0.0 ? 1.0 : p.beta;
-    if (!(beta > 0.0 && beta <= 1.0)) return fail(SINDI_E_INVALID, "%s: beta must be in (0, 1]", fn);
-    if (k < 1 || k > kGammaMax) return fail(SINDI_E_INVALID, "%s: k must be in [1, %d]", fn, kGammaMax);
-    int32_t gamma = rerank ? (p.gamma ? p.gamma : std::max(k, kDefaultGamma)) : k;
-    if (gamma < k || gamma > kGammaMax)
-        return fail(SINDI_E_INVALID, "%s: gamma must be in [k, %d]", fn, kGammaMax);
     if (qc->n_cols != ix->n_cols)
         return fail(SINDI_E_INVALID, "%s: queries have %lld columns, index has %lld", fn,
                     (long long)qc->n_cols, (long long)ix->n_cols);
-    const int batch = pick_batch(ix, p.batch);
-    if (batch < 1) return fail(SINDI_E_INVALID, "%s: batch must be 1, 2, 4 or 8", fn);
     if (qc->n_rows < 0 || qc->nnz < 0) return fail(SINDI_E_INVALID, "%s: bad query shape", fn);
     const int64_t nq = qc->n_rows;
-    if (nq == 0) return SINDI_OK;
     if (nq > INT32_MAX / 2) return fail(SINDI_E_INVALID, "%s: too many queries", fn);
+    Plan pl;
+    sindi_status st = make_plan(ix, nq, k, p, rerank, fn, pl);
+    if (st != SINDI_OK) return st;
+    if (nq == 0) return SINDI_OK;
+    if (qc->on_device && (!qc->indptr || (qc->nnz > 0 && (!qc->indices || !qc->values))))
+        return fail(SINDI_E_INVALID, "%s: null query array", fn);
+    if (!qc->on_device && (st = validate_host_csr(qc, "queries", kQueryHash / 2)) != SINDI_OK)
+        return st;
     std::lock_guard<std::mutex> lock(ix->mu);
+    Workspace &ws = ix->ws;
+    if ((st = reserve_workspace(ws, pl, nq, qc->nnz)) != SINDI_OK) return st;
 
     DevQueries dq{nq, qc->nnz, qc->indptr, qc->indices, qc->values};
     if (!qc->on_device) {
-        sindi_status st = validate_host_csr(qc, "queries", kQueryHash / 2);
-        if (st != SINDI_OK) return st;
-        HIP_TRY(ix->q_ptr.ensure((size_t)(nq + 1) * 8));
-        HIP_TRY(ix->q_idx.ensure((size_t)qc->nnz * 4 + 4));
-        HIP_TRY(ix->q_val.ensure((size_t)qc->nnz * 4 + 4));
-        HIP_TRY(hipMemcpyAsync(ix->q_ptr.p, qc->indptr, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(ws.q_ptr.ensure((size_t)(nq + 1) * 8));
+        HIP_TRY(ws.q_idx.ensure((size_t)qc->nnz * 4 + 4));
+        HIP_TRY(ws.q_val.ensure((size_t)qc->nnz * 4 + 4));
+        HIP_TRY(hipMemcpyAsync(ws.q_ptr.p, qc->indptr, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, s));
         if (qc->nnz) {
-            HIP_TRY(hipMemcpyAsync(ix->q_idx.p, qc->indices, (size_t)qc->nnz * 4, hipMemcpyHostToDevice, s));
-            HIP_TRY(hipMemcpyAsync(ix->q_val.p, qc->values, (size_t)qc->nnz * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(ws.q_idx.p, qc->indices, (size_t)qc->nnz * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(ws.q_val.p, qc->values, (size_t)qc->nnz * 4, hipMemcpyHostToDevice, s));
         }
-        dq.indptr = ix->q_ptr.as<int64_t>();
-        dq.indices = ix->q_idx.as<int32_t>();
-        dq.values = ix->q_val.as<float>();
-    } else if (!qc->indptr || (qc->nnz > 0 && (!qc->indices || !qc->values))) {
-        return fail(SINDI_E_INVALID, "%s: null query array", fn);
+        dq.indptr = ws.q_ptr.as<int64_t>();
+        dq.indices = ws.q_idx.as<int32_t>();
+        dq.values = ws.q_val.as<float>();
     }
-
-    // coarse query terms (beta-mass) and device-side validation
-    HIP_TRY(ix->ct.ensure((size_t)qc->nnz * 4 + 4));
-    HIP_TRY(ix->cw.ensure((size_t)qc->nnz * 4 + 4));
-    HIP_TRY(ix->cn.ensure((size_t)nq * 4));
-    HIP_TRY(ix->qinv.ensure((size_t)nq * 4));
-    HIP_TRY(ix->sabs.ensure(beta < 1.0 ? (size_t)qc->nnz * 8 + 8 : 8));
-    HIP_TRY(ix->err.ensure(4));
-    HIP_TRY(ix->status.ensure((size_t)nq * 4));
-    HIP_TRY(launch_fill_u32(ix->err.as<uint32_t>(), 1, 0u, s));
-    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>(), ix->qinv.as<float>()};
-    HIP_TRY(timed(kProfPrep, s, [&] {
-        return launch_query_prep(dq, ix->n_cols, beta, dc, ix->term_max.as<float>(),
-                                 ix->sabs.as<double>(), ix->err.as<int32_t>(), s);
-    }));
+    if ((st = enqueue_prep(ix, ws, pl, dq, s)) != SINDI_OK) return st;
     int32_t qerr = 0;
-    HIP_TRY(hipMemcpyAsync(&qerr, ix->err.p, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (qerr)
-        return fail(SINDI_E_INVALID,
-                    "%s: malformed query rows (flags 0x%x: 1 row pointers, 2 term id range, 4 order, "
-                    "8 non-finite, 16 more than %d entries)",
-                    fn, qerr, kQueryHash / 2);
-
-    const DevIndex dix = ix->dev();
-    if (ix->n_docs == 0) {
-        HIP_TRY(launch_fill_f32(out_scores, nq * k, -INFINITY, s));
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(out_ids), 2 * nq * k, 0xFFFFFFFFu, s));
+    if (qc->on_device) {
+        // device queries: validate before anything reaches the caller's outputs
+        HIP_TRY(hipMemcpyAsync(&qerr, ws.err.p, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        return SINDI_OK;
+        if (qerr)
+            return fail(SINDI_E_INVALID,
+                        "%s: malformed query rows (flags 0x%x: 1 row pointers, 2 term id range, "
+                        "4 order, 8 non-finite, 16 more than %d entries)",
+                        fn, qerr, kQueryHash / 2);
     }
-    const int32_t need = (int32_t)std::min<int64_t>(gamma, ix->n_docs);
-
-    // candidate threshold: sample tiles first, or keep every document
-    int64_t cap = p.cand_cap > 0 ? p.cand_cap : kDefaultCandCap;
-    cap = std::max<int64_t>(cap, need);
-    bool keep_all = p.sample_tiles < 0 || ix->n_docs <= cap;
-    if (keep_all) cap = ix->n_docs;
-    const int32_t n_sample =
-        keep_all ? 0 : (int32_t)std::min<int64_t>(ix->n_tiles, p.sample_tiles ? p.sample_tiles : kDefaultSampleTiles);
-    int64_t rank = 0, n_max = 0;
-    if (!keep_all) {
-        int64_t sampled = 0;
-        const std::vector<int64_t> &td = ix->h_tile_doc;
-        for (int64_t i = 0; i < n_sample; ++i) {
-            const int64_t t = i * ix->n_tiles / n_sample;
-            sampled += td[t + 1] - td[t];
-        }
-        const double f = (double)sampled / (double)ix->n_docs;
-        n_max = (int64_t)n_sample * kAccThreads;
-        rank = std::min<int64_t>(n_max, (int64_t)std::ceil(2.0 * need * f) + 8);
-    }
-    const int64_t group = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(kCandBudget / ((size_t)cap * 8))));
-    HIP_TRY(ix->cand.ensure((size_t)group * cap * 8));
-    HIP_TRY(ix->count.ensure((size_t)group * 4));
-    HIP_TRY(ix->theta.ensure((size_t)group * 4));
-    HIP_TRY(ix->slot_q.ensure((size_t)std::max<int64_t>(group, 1) * 4));
-    if (!keep_all) HIP_TRY(ix->maxima.ensure((size_t)group * n_max * 4));
-
-    std::vector<int32_t> rows((size_t)group);
-    for (int64_t g0 = 0; g0 < nq; g0 += group) {
-        const int32_t ns = (int32_t)std::min<int64_t>(group, nq - g0);
-        for (int32_t i = 0; i < ns; ++i) rows[i] = (int32_t)(g0 + i);
-        HIP_TRY(hipMemcpyAsync(ix->slot_q.p, rows.data(), (size_t)ns * 4, hipMemcpyHostToDevice, s));
-        if (keep_all) {
-            HIP_TRY(launch_fill_f32(ix->theta.as<float>(), ns, -INFINITY, s));
-        } else {
-            HIP_TRY(timed(kProfSample, s, [&] {
-                return launch_accumulate(dix, dq, dc, batch, true, ix->slot_q.as<int32_t>(), ns, n_sample,
-                                         ix->maxima.as<float>(), nullptr, nullptr, nullptr, 0, s);
-            }));
-            HIP_TRY(timed(kProfTheta, s, [&] {
-                return launch_theta(ix->maxima.as<float>(), n_max, rank, ns, ix->theta.as<float>(), s);
-            }));
-        }
-        HIP_TRY(launch_fill_u32(ix->count.as<uint32_t>(), ns, 0u, s));
-        HIP_TRY(timed(kProfScore, s, [&] {
-            return launch_accumulate(dix, dq, dc, batch, false, ix->slot_q.as<int32_t>(), ns, 0, nullptr,
-                                     ix->theta.as<float>(), ix->count.as<uint32_t>(),
-                                     ix->cand.as<uint64_t>(), cap, s);
-        }));
-        HIP_TRY(timed(kProfFinal, s, [&] {
-            return launch_finalize(dix, dq, ix->slot_q.as<int32_t>(), ns, ix->count.as<uint32_t>(),
-                                   ix->cand.as<uint64_t>(), cap, need, k, rerank, out_ids, out_scores,
-                                   ix->status.as<int32_t>(), s);
-        }));
-        // the host copy of rows[] must outlive the async upload above
-        HIP_TRY(hipStreamSynchronize(s));
-    }
+    if ((st = enqueue_search(ix, ws, pl, dq, out_ids, out_scores, s)) != SINDI_OK) return st;
     std::vector<int32_t> status((size_t)nq);
-    HIP_TRY(hipMemcpyAsync(status.data(), ix->status.p, (size_t)nq * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(status.data(), ws.status.p, (size_t)nq * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&qerr, ws.err.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (qerr) return fail(SINDI_E_INTERNAL, "%s: validated host queries flagged 0x%x", fn, qerr);
     std::vector<int32_t> retry;
     for (int64_t q = 0; q < nq; ++q)
         if (status[q] != kSlotOk) retry.push_back((int32_t)q);
-    if (!retry.empty()) {
-        // threshold missed gamma candidates or overflowed: keep every document
-        const int64_t cap_all = ix->n_docs;
-        const int64_t g_all = std::max<int64_t>(1, (int64_t)(kCandBudget / ((size_t)cap_all * 8)));
-        const int64_t gsz = std::min<int64_t>(g_all, (int64_t)retry.size());
-        HIP_TRY(ix->cand.ensure((size_t)gsz * cap_all * 8));
-        HIP_TRY(ix->count.ensure((size_t)gsz * 4));
-        HIP_TRY(ix->theta.ensure((size_t)gsz * 4));
-        HIP_TRY(ix->slot_q.ensure((size_t)gsz * 4));
-        for (size_t g0 = 0; g0 < retry.size(); g0 += (size_t)gsz) {
-            const int32_t ns = (int32_t)std::min<size_t>((size_t)gsz, retry.size() - g0);
-            HIP_TRY(hipMemcpyAsync(ix->slot_q.p, retry.data() + g0, (size_t)ns * 4, hipMemcpyHostToDevice, s));
-            HIP_TRY(launch_fill_f32(ix->theta.as<float>(), ns, -INFINITY, s));
-            HIP_TRY(launch_fill_u32(ix->count.as<uint32_t>(), ns, 0u, s));
-            HIP_TRY(timed(kProfScore, s, [&] {
-                return launch_accumulate(dix, dq, dc, 1, false, ix->slot_q.as<int32_t>(), ns, 0, nullptr,
-                                         ix->theta.as<float>(), ix->count.as<uint32_t>(),
-                                         ix->cand.as<uint64_t>(), cap_all, s);
-            }));
-            HIP_TRY(timed(kProfFinal, s, [&] {
-                return launch_finalize(dix, dq, ix->slot_q.as<int32_t>(), ns, ix->count.as<uint32_t>(),
-                                       ix->cand.as<uint64_t>(), cap_all, need, k, rerank, out_ids,
-                                       out_scores, ix->status.as<int32_t>(), s);
-            }));
-        }
-        HIP_TRY(hipMemcpyAsync(status.data(), ix->status.p, (size_t)nq * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        for (int32_t q : retry)
-            if (status[q] != kSlotOk) return fail(SINDI_E_INTERNAL, "%s: query %d unresolved", fn, q);
-    }
-    return SINDI_OK;
+    return retry_queries(ix, ws, pl, dq, retry, out_ids, out_scores, s, fn);
 }
 
 sindi_status check_dev_queries(sindi_index *ix, const sindi_csr *qc, const char *fn, hipStream_t s)
@@ -631,24 +625,56 @@ sindi_status check_dev_queries(sindi_index *ix, const sindi_csr *qc, const char 
     if (qc->n_cols != ix->n_cols) return fail(SINDI_E_INVALID, "%s: column count mismatch", fn);
     if (qc->n_rows < 0 || qc->nnz < 0) return fail(SINDI_E_INVALID, "%s: bad query shape", fn);
     if (qc->n_rows == 0) return SINDI_OK;
+    Workspace &ws = ix->ws;
     DevQueries dq{qc->n_rows, qc->nnz, qc->indptr, qc->indices, qc->values};
-    HIP_TRY(ix->ct.ensure((size_t)qc->nnz * 4 + 4));
-    HIP_TRY(ix->cw.ensure((size_t)qc->nnz * 4 + 4));
-    HIP_TRY(ix->cn.ensure((size_t)qc->n_rows * 4));
-    HIP_TRY(ix->qinv.ensure((size_t)qc->n_rows * 4));
-    HIP_TRY(ix->err.ensure(4));
-    HIP_TRY(launch_fill_u32(ix->err.as<uint32_t>(), 1, 0u, s));
-    DevCoarse dc{ix->ct.as<int32_t>(), ix->cw.as<float>(), ix->cn.as<int32_t>(), ix->qinv.as<float>()};
+    HIP_TRY(ws.ct.ensure((size_t)qc->nnz * 4 + 4));
+    HIP_TRY(ws.cw.ensure((size_t)qc->nnz * 4 + 4));
+    HIP_TRY(ws.cn.ensure((size_t)qc->n_rows * 4));
+    HIP_TRY(ws.qinv.ensure((size_t)qc->n_rows * 4));
+    HIP_TRY(ws.err.ensure(4));
+    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 1, 0u, s));
+    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
     HIP_TRY(launch_query_prep(dq, ix->n_cols, 1.0, dc, ix->term_max.as<float>(), nullptr,
-                              ix->err.as<int32_t>(), s));
+                              ws.err.as<int32_t>(), s));
     int32_t qerr = 0;
-    HIP_TRY(hipMemcpyAsync(&qerr, ix->err.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&qerr, ws.err.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (qerr) return fail(SINDI_E_INVALID, "%s: malformed query rows (flags 0x%x)", fn, qerr);
     return SINDI_OK;
 }
 
 }  // namespace
+}  // namespace sindi
+
+sindi::DevIndex sindi_index::dev() const
+{
+    sindi::DevIndex d;
+    d.n_docs = n_docs;
+    d.n_cols = n_cols;
+    d.n_tiles = n_tiles;
+    d.tile_stride = tile_stride;
+    d.value_dtype = dtype;
+    d.tile_doc = tile_doc.as<int64_t>();
+    d.tile_post = tile_post.as<int64_t>();
+    d.term_off = term_off.as<uint32_t>();
+    d.post_doc = post_doc.as<uint16_t>();
+    d.post_val = post_val.p;
+    d.term_max = term_max.as<float>();
+    d.indptr = indptr.as<int64_t>();
+    d.indices = indices.as<int32_t>();
+    d.values = values.as<float>();
+    d.nnz = nnz;
+    return d;
+}
+
+int64_t sindi_index::device_bytes() const
+{
+    return (int64_t)(indptr.bytes + indices.bytes + values.bytes + tile_doc.bytes +
+                     tile_post.bytes + term_off.bytes + post_doc.bytes + post_val.bytes +
+                     term_max.bytes);
+}
+
+using namespace sindi;
 
 // ------------------------------------------------------------------ C ABI
 extern "C" {
@@ -759,43 +785,12 @@ sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queri
     return SINDI_OK;
 }
 
-sindi_status sindi_profile_enable(int32_t enable)
-{
-    g_prof.on.store(enable != 0);
-    return SINDI_OK;
-}
+sindi_status sindi_profile_enable(int32_t enable) { return profile_enable(enable); }
 
-sindi_status sindi_profile_read(sindi_profile *out, int32_t reset)
-{
-    std::lock_guard<std::mutex> lock(g_prof.mu);
-    sindi_status st = SINDI_OK;
-    for (auto &r : g_prof.pending) {
-        float ms = 0.0f;
-        hipError_t e = hipEventSynchronize(r.b);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
-        if (e != hipSuccess && st == SINDI_OK)
-            st = fail(SINDI_E_HIP, "sindi_profile_read: %s", hipGetErrorString(e));
-        g_prof.n[r.cat] += 1;
-        g_prof.ms[r.cat] += ms;
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-    }
-    g_prof.pending.clear();
-    if (out)
-        for (int i = 0; i < 5; ++i) {
-            out->launches[i] = g_prof.n[i];
-            out->ms[i] = g_prof.ms[i];
-        }
-    if (reset)
-        for (int i = 0; i < 5; ++i) {
-            g_prof.n[i] = 0;
-            g_prof.ms[i] = 0.0;
-        }
-    return st;
-}
+sindi_status sindi_profile_read(sindi_profile *out, int32_t reset) { return profile_read(out, reset); }
 
-const char *sindi_last_error(void) { return g_err.c_str(); }
+const char *sindi_last_error(void) { return last_error(); }
 
-const char *sindi_version(void) { return "sindi-mi355x 0.1 (gfx950)"; }
+const char *sindi_version(void) { return "sindi-mi355x 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -75,13 +75,16 @@ hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, D
 hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                              int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
                              int32_t n_sample_tiles, float *maxima, const float *theta,
-                             uint32_t *count, uint64_t *cand, int64_t cap, hipStream_t s);
+                             uint32_t *count, uint64_t *cand, int64_t cap, int32_t tiles_per_wg,
+                             hipStream_t s);
 
 hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,
                         float *theta, hipStream_t s);
 
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+// p[i] = first + i for i in [0, n).
+hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s);
 
 hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
                            int32_t n_slots, const uint32_t *count, const uint64_t *cand,

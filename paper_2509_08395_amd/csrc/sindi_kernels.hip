@@ -399,7 +399,7 @@ template <int VT, int B, bool SAMPLE>
 __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
     int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
-    int64_t cap)
+    int64_t cap, int32_t tiles_per_wg)
 {
     constexpr int NT = kAccThreads, NW = NT / kWave, EB = kEntryBlock;
     constexpr bool PACK = B >= 2;
@@ -513,7 +513,12 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     // the next tile while the current tile accumulates.
     uint32_t pre_lo = 0, pre_hi = 0;
     bool have_pre = false;
-    for (int64_t ti = blockIdx.y; ti < n_tile_iter; ti += gridDim.y) {
+    // Workgroup y sweeps tiles [y R, (y + 1) R).  Workgroups are dispatched batch
+    // fastest, so those resident together walk the same tiles at about the
+    // same pace and share the tiles' lists in L2.
+    const int64_t ti_beg = (int64_t)blockIdx.y * tiles_per_wg;
+    const int64_t ti_end = min(n_tile_iter, ti_beg + tiles_per_wg);
+    for (int64_t ti = ti_beg; ti < ti_end; ++ti) {
         const int64_t t = SAMPLE ? (ti * ix.n_tiles / n_sample) : ti;
         const int64_t d0 = ix.tile_doc[t];
         const int32_t len = (int32_t)(ix.tile_doc[t + 1] - d0);
@@ -553,8 +558,8 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
             if (tid == 0) gp[nu] = total;
             have_pre = false;
             if (n_blocks == 1) {
-                const int64_t tn = ti + gridDim.y;
-                if (tn < n_tile_iter) {
+                const int64_t tn = ti + 1;
+                if (tn < ti_end) {
                     have_pre = true;
                     if (tid < nu) {
                         const int64_t t2 = SAMPLE ? (tn * ix.n_tiles / n_sample) : tn;
@@ -751,6 +756,11 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+__global__ void k_iota_i32(int32_t *p, int32_t n, int32_t first)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = first + i;
 }
 
 // ------------------------------------------------------------------ finalize
@@ -969,22 +979,26 @@ template <int VT, int B, bool SAMPLE>
 hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                           const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
                           const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
-                          hipStream_t s)
+                          int32_t tiles_per_wg, hipStream_t s)
 {
     const size_t lds = accumulate_lds_bytes(B, ix.tile_stride);
     hipError_t e = set_lds(k_accumulate<VT, B, SAMPLE>, lds);
     if (e != hipSuccess) return e;
     const int64_t n_batches = (n_slots + B - 1) / B;
     const int64_t n_iter = SAMPLE ? n_sample : ix.n_tiles;
-    // Tiles are dealt to workgroups round-robin: enough workgroups to fill the
-    // chip several times over, each sweeping its tiles in ascending order so
-    // that the workgroups in flight read the same tiles' lists at the same time.
-    int64_t groups = (8192 + n_batches - 1) / n_batches;
-    groups = groups < 1 ? 1 : (groups > n_iter ? n_iter : groups);
-    if (groups > 65535) groups = 65535;
+    // Contiguous tile ranges per workgroup (see the kernel); the range length
+    // keeps the grid at least a few times the chip's resident workgroups.
+    int64_t per = tiles_per_wg > 0 ? tiles_per_wg : 8;
+    while (per > 1 && n_batches * ((n_iter + per - 1) / per) < 4096) per >>= 1;
+    int64_t groups = (n_iter + per - 1) / per;
+    if (groups > 65535) {
+        groups = 65535;
+        per = (n_iter + groups - 1) / groups;
+        groups = (n_iter + per - 1) / per;
+    }
     dim3 grid((unsigned)n_batches, (unsigned)groups);
     hipLaunchKernelGGL((k_accumulate<VT, B, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
-                       slot_q, n_slots, n_sample, maxima, theta, count, cand, cap);
+                       slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, (int32_t)per);
     return hipGetLastError();
 }
 
@@ -992,13 +1006,13 @@ template <int VT, bool SAMPLE>
 hipError_t dispatch_b(int batch, const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                       const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
                       const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
-                      hipStream_t s)
+                      int32_t tiles_per_wg, hipStream_t s)
 {
     switch (batch) {
-    case 1: return run_accumulate<VT, 1, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
-    case 2: return run_accumulate<VT, 2, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
-    case 4: return run_accumulate<VT, 4, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
-    case 8: return run_accumulate<VT, 8, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, s);
+    case 1: return run_accumulate<VT, 1, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
+    case 2: return run_accumulate<VT, 2, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
+    case 4: return run_accumulate<VT, 4, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
+    case 8: return run_accumulate<VT, 8, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1019,18 +1033,19 @@ hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, D
 hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                              int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
                              int32_t n_sample_tiles, float *maxima, const float *theta,
-                             uint32_t *count, uint64_t *cand, int64_t cap, hipStream_t s)
+                             uint32_t *count, uint64_t *cand, int64_t cap, int32_t tiles_per_wg,
+                             hipStream_t s)
 {
     if (n_slots == 0 || ix.n_tiles == 0) return hipSuccess;
     const int vt = ix.value_dtype;
     if (sample) {
-        if (vt == 0) return dispatch_b<0, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
-        if (vt == 1) return dispatch_b<1, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
-        return dispatch_b<2, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+        if (vt == 0) return dispatch_b<0, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
+        if (vt == 1) return dispatch_b<1, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
+        return dispatch_b<2, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
     }
-    if (vt == 0) return dispatch_b<0, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
-    if (vt == 1) return dispatch_b<1, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
-    return dispatch_b<2, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, s);
+    if (vt == 0) return dispatch_b<0, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
+    if (vt == 1) return dispatch_b<1, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
+    return dispatch_b<2, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
 }
 
 hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,
@@ -1056,6 +1071,15 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int32_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, first);
     return hipGetLastError();
 }
 

@@ -1,0 +1,91 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+The 1M-document pruned workload is checked on every query; the 8.8M-document workload
+(FP16 postings) on sampled queries that the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from parity import check_ranked, check_same_topk, check_scores, score_scale
+from synth.workloads import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sindi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_08395_amd as s
+    s._lib.load()
+    return s
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _kth_tol(corpus, queries, ref_ids, rtol):
+    nq = ref_ids.shape[0]
+    last = np.array([r[r >= 0][-1] for r in ref_ids])
+    return 2.0 * rtol * score_scale(corpus, queries, np.arange(nq), last)
+
+
+def _pool_margin(pool_ids, pool_sc, cp, qp, rtol):
+    def f(r, d):
+        valid = pool_ids[r] >= 0
+        last, lastid = pool_sc[r][valid][-1], pool_ids[r][valid][-1]
+        c = oracle.pair_scores(cp, qp, [r], [d])[0]
+        sc = score_scale(cp, qp, [r, r], [d, lastid]).max()
+        return abs(c - last) <= 2 * rtol * sc
+    return f
+
+
+def _run(sindi, wl, corpus, queries, dtype):
+    idx = sindi.Index(corpus, alpha=wl.alpha, window=wl.window, value_dtype=dtype)
+    ids, sc = idx.search(sindi.DeviceCsr.from_host(queries), wl.k, beta=wl.beta, gamma=wl.gamma)
+    return idx, _np(ids), _np(sc)
+
+
+def test_pruned_1m_every_query(sindi):
+    wl = WORKLOADS["pruned-1m"]
+    corpus, queries = wl.corpus(), wl.queries()
+    idx, ids, sc = _run(sindi, wl, corpus, queries, wl.value_dtype)
+    keep = oracle.mass_prune(corpus, wl.alpha)
+    ref = oracle.build_index(corpus, wl.window, keep)
+    rid, rsc, pid, psc = oracle.approx_search(ref, corpus, queries, wl.beta, wl.gamma, wl.k,
+                                              want_pool=True)
+    check_ranked(ids, sc)
+    check_scores(corpus, queries, ids, sc, rtol=1e-5)
+    cp = oracle.apply_mask(corpus, keep)
+    check_same_topk(ids, rid, rsc, _kth_tol(corpus, queries, rid, 1e-5),
+                    pool_margin=_pool_margin(pid, psc, cp, queries, 1e-5))
+    truth, _ = oracle.exact_topk(corpus, queries.take_rows(np.arange(0, 1000, 10)), wl.k)
+    assert oracle.recall_at_k(ids[::10], truth) >= 0.99
+
+
+@pytest.mark.parametrize("dtype,coarse_rtol", [("f16", 2e-3)])
+def test_splade_8_8m_sampled_queries(sindi, dtype, coarse_rtol):
+    wl = WORKLOADS["splade-8.8m"]
+    corpus, queries = wl.corpus(), wl.queries()
+    idx, ids, sc = _run(sindi, wl, corpus, queries, dtype)
+    del idx
+    check_ranked(ids, sc)
+    sel = np.linspace(0, wl.n_queries - 1, 24).astype(np.int64)
+    qs = queries.take_rows(sel)
+    gi, gs = ids[sel], sc[sel]
+    check_scores(corpus, qs, gi, gs, rtol=1e-5)  # FP32 rerank from the FP32 unpruned rows
+    keep = oracle.mass_prune(corpus, wl.alpha)
+    ref = oracle.build_index(corpus, wl.window, keep)
+    rid, rsc, pid, psc = oracle.approx_search(ref, corpus, qs, wl.beta, wl.gamma, wl.k,
+                                              want_pool=True)
+    del ref
+    cp = oracle.apply_mask(corpus, keep)
+    del keep
+    check_same_topk(gi, rid, rsc, _kth_tol(corpus, qs, rid, 1e-5),
+                    pool_margin=_pool_margin(pid, psc, cp, qs, coarse_rtol))
+    truth, _ = oracle.exact_topk(corpus, qs.take_rows(np.arange(0, 24, 3)), wl.k)
+    assert oracle.recall_at_k(gi[::3], truth) >= 0.99
