@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--recall-queries", type=int, default=128)
     ap.add_argument("--oracle-queries", type=int, default=7000)
     ap.add_argument("--no-oracle", action="store_true", help="skip recall and the CPU baseline")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="open-loop serving run per arrival rate (0: skip serving)")
+    ap.add_argument("--serve-rates", default="",
+                    help="comma-separated arrival rates, queries/s (default: the serving workload's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -193,6 +197,11 @@ def main():
     }
     roofline["traffic"] = measured_traffic(result["config"])
 
+    if args.serve_seconds > 0 and dtype == "f16" and wl.name == "splade-8.8m":
+        result["serving"] = serving_leg(sindi, idx, args)
+        result["latency_p99_ms"] = {str(int(r["offered_qps"])): r["p99_ms"]
+                                    for r in result["serving"]["rates"]}
+
     if not args.no_oracle:
         import oracle  # CPU baseline and recall only
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -226,6 +235,42 @@ def main():
         if rec < 0.99:
             result["note"] = f"recall {rec:.4f} below 0.99"
     print(json.dumps(result), flush=True)
+
+
+def serving_leg(sindi, idx, args):
+    """Open-loop Poisson arrivals at each rate into the continuous-batching server over the
+    same index; latency = completion on the host minus scheduled arrival."""
+    from synth.workloads import WORKLOADS
+    wl = WORKLOADS["serving"]
+    rates = ([float(x) for x in args.serve_rates.split(",")] if args.serve_rates
+             else list(wl.extra["rates"]))
+    out = []
+    row0 = 0
+    with sindi.Server(idx, max_inflight=2, max_batch=512, k_max=100, gamma=wl.gamma) as srv:
+        for i, rate in enumerate(rates):
+            n = max(1, int(rate * args.serve_seconds))
+            q = wl.queries(n, row0=row0)
+            ks = wl.request_ks(n, row0=row0)
+            arr = wl.arrivals(rate, n, block=i)
+            row0 += n
+            st0 = srv.stats()
+            ids, sc, lat = srv.replay(q, ks, arr)
+            st1 = srv.stats()
+            lat_ms = lat / 1e6
+            # completion instants relative to the start of the replay
+            span = float(np.max(arr + lat / 1e9))
+            batches = st1["batches"] - st0["batches"]
+            rec = {"offered_qps": rate, "requests": n, "achieved_qps": round(n / span, 1),
+                   "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                   "max_ms": round(float(lat_ms.max()), 3),
+                   "mean_batch": round(n / max(batches, 1), 1),
+                   "retried": st1["retried"] - st0["retried"]}
+            log(f"serving {rec}")
+            out.append(rec)
+    return {"workload": "serving", "query_nnz": "uniform 5..200", "k": "uniform {10, 50, 100}",
+            "gamma": wl.gamma, "seconds_per_rate": args.serve_seconds, "max_inflight": 2,
+            "max_batch": 512, "rates": out}
 
 
 def _cpu_model():

@@ -30,6 +30,7 @@ typedef enum {
     SINDI_E_RANGE = -2,    /* a value does not fit the requested storage type   */
     SINDI_E_OOM = -3,      /* device or host allocation failed                  */
     SINDI_E_HIP = -4,      /* a HIP runtime call failed                         */
+    SINDI_E_BUSY = -5,     /* serving: request queue full, or result not ready  */
     SINDI_E_INTERNAL = -6  /* a library invariant failed                        */
 } sindi_status;
 
@@ -176,6 +177,85 @@ sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queri
                                   const int64_t *cand_ids, int32_t n_cand,
                                   const float *grad_scores, float *grad_query_values,
                                   float *grad_doc_values, void *stream);
+
+/*
+ * ---------------------------------------------------------------- serving
+ * Continuous batching over one index (the paper measures single queries;
+ * this is the request loop around Alg. 4).  Requests are queued as they
+ * arrive; a dispatcher thread owned by the server takes every queued request
+ * (up to max_batch) into a batch as soon as one of max_inflight batch slots
+ * is free, and runs the whole search of that batch asynchronously on the
+ * slot's own HIP stream, so batches overlap on the device.  A batch runs with
+ * the largest k any of its requests asks for; every request gets the prefix
+ * of its own k.  Scoring is deterministic and independent of which other
+ * queries share a batch, so a request's result equals what sindi_search
+ * returns for the same query alone (bit for bit, ids and scores).
+ * The server holds its device workspace (candidate buffers, query staging,
+ * outputs) for its whole life; the index must outlive the server.
+ */
+typedef struct {
+    int32_t max_inflight;     /* batches on the device at once (streams); 0 -> 2, at most 8 */
+    int32_t max_batch;        /* queries per batch; 0 -> 256, at most 8192                   */
+    int32_t k_max;            /* largest k of a request, <= gamma; 0 -> 100                  */
+    int32_t max_query_nnz;    /* longest query row accepted; 0 -> 512, at most 4096          */
+    int64_t max_queue;        /* queued requests before submit returns SINDI_E_BUSY; 0 -> 2^20 */
+    int64_t workspace_bytes;  /* candidate buffer bytes per slot; 0 -> 1 GiB                 */
+    sindi_search_params search;  /* beta, gamma, cand_cap, sample_tiles, tile_run as for
+                                    sindi_search; gamma 0 -> max(k_max, 500)                 */
+} sindi_server_params;
+
+/* Counters since creation. */
+typedef struct {
+    int64_t submitted, completed, batches, retried, largest_batch;
+    double busy_ms;           /* wall time with at least one batch on the device          */
+} sindi_server_stats;
+
+typedef struct sindi_server sindi_server;
+
+/* Create a server on the current HIP device (the index's device).  Allocates
+ * the per-slot device workspace and pinned host staging, starts the
+ * dispatcher thread. */
+sindi_status sindi_server_create(const sindi_index *idx, const sindi_server_params *params,
+                                 sindi_server **out);
+
+/*
+ * Queue one query: nnz entries, host memory, term ids strictly ascending in
+ * [0, n_cols), finite values (Def. 1), 1 <= k <= k_max.  The entries are
+ * copied before the call returns.  *ticket identifies the request for
+ * sindi_server_wait.  SINDI_E_BUSY: max_queue requests are already waiting.
+ * Thread-safe.
+ */
+sindi_status sindi_server_submit(sindi_server *srv, const int32_t *indices, const float *values,
+                                 int32_t nnz, int32_t k, int64_t *ticket);
+
+/*
+ * Wait up to timeout_ms (< 0: without limit) for a request and collect it:
+ * its k ids and scores into host buffers (ids -1 / scores -inf beyond the
+ * corpus size) and the time from submit to completion in nanoseconds (any
+ * output pointer may be NULL).  A collected ticket is forgotten.
+ * SINDI_E_BUSY: not finished within the timeout (the ticket stays valid).
+ * A request whose batch failed returns that batch's error.  Thread-safe.
+ */
+sindi_status sindi_server_wait(sindi_server *srv, int64_t ticket, int64_t *ids, float *scores,
+                               int64_t *latency_ns, double timeout_ms);
+
+/*
+ * Open-loop replay: submit query row r of `queries` (host CSR) with k = ks[r]
+ * at arrival_s[r] seconds (non-decreasing) after the call starts, whatever
+ * the server's progress, then wait for every request.  Outputs (host memory):
+ * out_ids / out_scores [n_rows * k_max], row r holding its ks[r] results
+ * first (the rest -1 / -inf); latency_ns [n_rows] = completion minus the
+ * scheduled arrival (so queueing behind a late submit counts).  Blocks.
+ */
+sindi_status sindi_server_replay(sindi_server *srv, const sindi_csr *queries, const int32_t *ks,
+                                 const double *arrival_s, int64_t *out_ids, float *out_scores,
+                                 int64_t *latency_ns);
+
+sindi_status sindi_server_get_stats(const sindi_server *srv, sindi_server_stats *out);
+
+/* Stop the dispatcher after the batches on the device finish; requests not
+ * yet collected are dropped.  Releases everything the server holds. */
+void sindi_server_destroy(sindi_server *srv);
 
 /*
  * Kernel timing.  While enabled, the library records a pair of HIP events on

@@ -20,8 +20,8 @@ import numpy as np
 from . import _lib
 from ._lib import DTYPES, SindiError  # noqa: F401
 
-__all__ = ["Index", "DeviceCsr", "SindiScore", "SindiError", "version", "profile_enable",
-           "profile_read"]
+__all__ = ["Index", "Server", "DeviceCsr", "SindiScore", "SindiError", "version",
+           "profile_enable", "profile_read"]
 
 
 def version() -> str:
@@ -204,6 +204,92 @@ class Index:
                                                     int(cand.shape[1]), ptr(grad),
                                                     ptr(grad_query), ptr(grad_doc),
                                                     _stream(stream)))
+
+
+class Server:
+    """Continuous batching over an Index (include/sindi.h, serving section).
+
+    Requests queue as they arrive; the library's dispatcher thread runs every queued
+    request (up to ``max_batch``) as one batch on one of ``max_inflight`` streams as soon
+    as a stream is free.  Results are host numpy arrays.
+    """
+
+    def __init__(self, index, max_inflight=2, max_batch=256, k_max=100, max_query_nnz=512,
+                 max_queue=0, workspace_bytes=0, beta=1.0, gamma=0, batch=0, cand_cap=0,
+                 sample_tiles=0, tile_run=0):
+        lib = _lib.load()
+        sp = _lib.SindiSearchParams(float(beta), int(gamma), int(batch), int(cand_cap),
+                                    int(sample_tiles), int(tile_run))
+        params = _lib.SindiServerParams(int(max_inflight), int(max_batch), int(k_max),
+                                        int(max_query_nnz), int(max_queue), int(workspace_bytes),
+                                        sp)
+        handle = ctypes.c_void_p()
+        _lib.check(lib.sindi_server_create(index._h, ctypes.byref(params), ctypes.byref(handle)))
+        self._h = handle
+        self._index = index  # the index must outlive the server
+        self.k_max = int(k_max)
+
+    def submit(self, indices, values, k) -> int:
+        """Queue one query (ascending term ids, float values); returns its ticket."""
+        idx = np.ascontiguousarray(indices, dtype=np.int32)
+        val = np.ascontiguousarray(values, dtype=np.float32)
+        if idx.shape != val.shape:
+            raise ValueError("indices and values differ in length")
+        t = ctypes.c_int64()
+        _lib.check(_lib.load().sindi_server_submit(self._h, idx.ctypes.data, val.ctypes.data,
+                                                   int(idx.shape[0]), int(k), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket, k, timeout_ms=-1.0):
+        """(ids int64 [k], scores float32 [k], latency in ns) of a submitted request."""
+        ids = np.empty(k, np.int64)
+        scores = np.empty(k, np.float32)
+        lat = ctypes.c_int64()
+        _lib.check(_lib.load().sindi_server_wait(self._h, int(ticket), ids.ctypes.data,
+                                                 scores.ctypes.data, ctypes.byref(lat),
+                                                 float(timeout_ms)))
+        return ids, scores, lat.value
+
+    def replay(self, queries, ks, arrival_s):
+        """Open-loop replay: row r arrives arrival_s[r] seconds after the call starts.
+        Returns ids [n, k_max], scores [n, k_max] (row r's first ks[r] entries hold its
+        results) and latency_ns [n] measured from the scheduled arrival."""
+        h = _HostCsr(queries)
+        n = h.n_rows
+        ks = np.ascontiguousarray(ks, dtype=np.int32)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        if ks.shape != (n,) or arr.shape != (n,):
+            raise ValueError("ks and arrival_s need one entry per query")
+        ids = np.empty((n, self.k_max), np.int64)
+        scores = np.empty((n, self.k_max), np.float32)
+        lat = np.empty(n, np.int64)
+        _lib.check(_lib.load().sindi_server_replay(self._h, ctypes.byref(h.struct()),
+                                                   ks.ctypes.data, arr.ctypes.data,
+                                                   ids.ctypes.data, scores.ctypes.data,
+                                                   lat.ctypes.data))
+        return ids, scores, lat
+
+    def stats(self) -> dict:
+        st = _lib.SindiServerStats()
+        _lib.check(_lib.load().sindi_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().sindi_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _make_score_fn():

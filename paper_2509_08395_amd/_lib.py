@@ -7,8 +7,8 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsindi.so")
 
-SINDI_OK, SINDI_E_INVALID, SINDI_E_RANGE, SINDI_E_OOM, SINDI_E_HIP, SINDI_E_INTERNAL = (
-    0, -1, -2, -3, -4, -6)
+SINDI_OK, SINDI_E_INVALID, SINDI_E_RANGE, SINDI_E_OOM, SINDI_E_HIP, SINDI_E_BUSY, SINDI_E_INTERNAL = (
+    0, -1, -2, -3, -4, -5, -6)
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 VALUE_BYTES = {0: 4, 1: 2, 2: 2}
 
@@ -40,6 +40,19 @@ class SindiIndexInfo(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
 
 
+class SindiServerParams(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("k_max", ctypes.c_int32), ("max_query_nnz", ctypes.c_int32),
+                ("max_queue", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("search", SindiSearchParams)]
+
+
+class SindiServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("retried", ctypes.c_int64),
+                ("largest_batch", ctypes.c_int64), ("busy_ms", ctypes.c_double)]
+
+
 class SindiProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 5), ("ms", ctypes.c_double * 5)]
 
@@ -49,6 +62,8 @@ PROFILE_CLASSES = ("query_prep", "accumulate_threshold", "accumulate_score", "th
 
 EXPORTS = ("sindi_build", "sindi_index_free", "sindi_index_get_info", "sindi_index_export",
            "sindi_search", "sindi_search_coarse", "sindi_score_forward", "sindi_score_backward",
+           "sindi_server_create", "sindi_server_submit", "sindi_server_wait",
+           "sindi_server_replay", "sindi_server_get_stats", "sindi_server_destroy",
            "sindi_profile_enable", "sindi_profile_read", "sindi_last_error", "sindi_version")
 
 
@@ -89,6 +104,16 @@ def load():
               lib.sindi_search, lib.sindi_search_coarse, lib.sindi_score_forward,
               lib.sindi_score_backward):
         f.restype = ctypes.c_int
+    lib.sindi_server_create.argtypes = [P, ctypes.POINTER(SindiServerParams), ctypes.POINTER(P)]
+    lib.sindi_server_submit.argtypes = [P, P, P, I32, I32, ctypes.POINTER(I64)]
+    lib.sindi_server_wait.argtypes = [P, I64, P, P, ctypes.POINTER(I64), ctypes.c_double]
+    lib.sindi_server_replay.argtypes = [P, ctypes.POINTER(SindiCsr), P, P, P, P, P]
+    lib.sindi_server_get_stats.argtypes = [P, ctypes.POINTER(SindiServerStats)]
+    for f in (lib.sindi_server_create, lib.sindi_server_submit, lib.sindi_server_wait,
+              lib.sindi_server_replay, lib.sindi_server_get_stats):
+        f.restype = ctypes.c_int
+    lib.sindi_server_destroy.argtypes = [P]
+    lib.sindi_server_destroy.restype = None
     lib.sindi_profile_enable.argtypes = [I32]
     lib.sindi_profile_enable.restype = ctypes.c_int
     lib.sindi_profile_read.argtypes = [ctypes.POINTER(SindiProfile), I32]

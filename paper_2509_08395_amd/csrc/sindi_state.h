@@ -19,6 +19,8 @@ namespace sindi {
 
 // Record a thread-local error message and return st.
 sindi_status fail(sindi_status st, const char *fmt, ...);
+// This thread's last error message.
+const char *last_error();
 
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \

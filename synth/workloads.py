@@ -11,6 +11,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
 
+import numpy as np
+
 import synth
 
 
@@ -49,6 +51,18 @@ class Workload:
                               nnz=self.query_nnz, clip=self.clip, terms=self.terms,
                               values=self.values, seed=self.seed,
                               stream=synth.STREAM_QUERIES, row0=row0)
+
+    def arrivals(self, rate: float, n: int, block: int = 0) -> np.ndarray:
+        """Open-loop Poisson arrival times in seconds: n requests at `rate` per second
+        (exponential gaps); `block` selects an independent run of draws."""
+        gaps = synth.exponential_f64(n, self.seed, synth.STREAM_ARRIVALS, 1.0 / rate,
+                                     i0=block << 32)
+        return np.cumsum(gaps)
+
+    def request_ks(self, n: int, choices=(10, 50, 100), row0: int = 0) -> np.ndarray:
+        """k of each serving request, uniform over `choices`."""
+        u = synth.uniform_u64(n, self.seed, synth.STREAM_ARRIVALS, i0=(1 << 48) + row0)
+        return np.asarray(choices, np.int32)[(u % np.uint64(len(choices))).astype(np.int64)]
 
 
 WORKLOADS = {

@@ -90,3 +90,49 @@ def test_null_arguments_are_errors_not_crashes():
     assert lib.sindi_index_get_info(None, None) == _lib.SINDI_E_INVALID
     assert lib.sindi_score_forward(None, None, None, 0, None, None) == _lib.SINDI_E_INVALID
     lib.sindi_index_free(None)
+
+
+def test_server_null_arguments_are_errors_not_crashes():
+    from paper_2509_08395_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    t = ctypes.c_int64()
+    assert lib.sindi_server_create(None, None, ctypes.byref(h)) == _lib.SINDI_E_INVALID
+    assert lib.sindi_server_submit(None, None, None, 0, 10, ctypes.byref(t)) == _lib.SINDI_E_INVALID
+    assert lib.sindi_server_wait(None, 0, None, None, None, 0.0) == _lib.SINDI_E_INVALID
+    assert lib.sindi_server_replay(None, None, None, None, None, None, None) == _lib.SINDI_E_INVALID
+    assert lib.sindi_server_get_stats(None, None) == _lib.SINDI_E_INVALID
+    lib.sindi_server_destroy(None)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors have the C structs' sizes and field offsets (gcc on the header)."""
+    import shutil
+    import subprocess
+    from paper_2509_08395_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = {"sindi_csr": _lib.SindiCsr, "sindi_build_params": _lib.SindiBuildParams,
+               "sindi_search_params": _lib.SindiSearchParams,
+               "sindi_index_info": _lib.SindiIndexInfo,
+               "sindi_server_params": _lib.SindiServerParams,
+               "sindi_server_stats": _lib.SindiServerStats, "sindi_profile": _lib.SindiProfile}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sindi.h"', 'int main(void) {']
+    for c, py in structs.items():
+        lines.append(f'printf("{c} size %zu\\n", sizeof({c}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{c} {f} %zu\\n", offsetof({c}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for c, py in structs.items():
+        assert got[(c, "size")] == ctypes.sizeof(py), c
+        for f, _ in py._fields_:
+            assert got[(c, f)] == getattr(py, f).offset, (c, f)

@@ -1,0 +1,133 @@
+"""Serving form: continuous batching returns, for every request, exactly what the search
+returns for the same query alone (scoring is deterministic and independent of the mix),
+and every returned score is the exact inner product of that document within 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+from parity import check_ranked, check_scores
+from synth.workloads import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sindi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_08395_amd as s
+    s._lib.load()
+    return s
+
+
+@pytest.fixture(scope="module")
+def setup(sindi):
+    wl = WORKLOADS["serving"].scaled(40_000, 240)
+    corpus, queries = wl.corpus(), wl.queries()
+    idx = sindi.Index(corpus, alpha=wl.alpha, window=10_000, value_dtype="f16", tile=4096)
+    ks = wl.request_ks(queries.n_rows)
+    # reference: grouped by k, one search call per group
+    ref_ids = np.full((queries.n_rows, 100), -1, np.int64)
+    ref_sc = np.full((queries.n_rows, 100), -np.inf, np.float32)
+    for k in (10, 50, 100):
+        rows = np.nonzero(ks == k)[0]
+        ids, sc = idx.search(queries.take_rows(rows), int(k), gamma=wl.gamma)
+        ref_ids[rows, :k] = ids.cpu().numpy()
+        ref_sc[rows, :k] = sc.cpu().numpy()
+    return wl, corpus, queries, idx, ks, ref_ids, ref_sc
+
+
+def _same(a_ids, a_sc, b_ids, b_sc):
+    assert np.array_equal(a_ids, b_ids)
+    assert np.array_equal(a_sc.view(np.uint32), b_sc.view(np.uint32))
+
+
+def test_reference_is_search_alone(sindi, setup):
+    """The per-k group calls agree bit for bit with one call per query."""
+    wl, corpus, queries, idx, ks, ref_ids, ref_sc = setup
+    for r in range(0, queries.n_rows, 20):
+        k = int(ks[r])
+        ids, sc = idx.search(queries.take_rows([r]), k, gamma=wl.gamma)
+        _same(ids.cpu().numpy()[0], sc.cpu().numpy()[0], ref_ids[r, :k], ref_sc[r, :k])
+
+
+def test_submit_wait_identical_to_search(sindi, setup):
+    wl, corpus, queries, idx, ks, ref_ids, ref_sc = setup
+    with sindi.Server(idx, max_inflight=3, max_batch=64, k_max=100, gamma=wl.gamma) as srv:
+        tickets = []
+        for r in range(queries.n_rows):
+            a, b = queries.indptr[r], queries.indptr[r + 1]
+            tickets.append(srv.submit(queries.indices[a:b], queries.values[a:b], int(ks[r])))
+        for r, t in enumerate(tickets):
+            k = int(ks[r])
+            ids, sc, lat = srv.wait(t, k)
+            _same(ids, sc, ref_ids[r, :k], ref_sc[r, :k])
+            assert lat > 0
+        st = srv.stats()
+    assert st["submitted"] == st["completed"] == queries.n_rows
+    assert 1 <= st["batches"] <= queries.n_rows and st["largest_batch"] <= 64
+
+
+def test_replay_identical_and_scores_exact(sindi, setup):
+    wl, corpus, queries, idx, ks, ref_ids, ref_sc = setup
+    arr = wl.arrivals(20_000.0, queries.n_rows)
+    with sindi.Server(idx, max_inflight=2, max_batch=32, k_max=100, gamma=wl.gamma) as srv:
+        ids, sc, lat = srv.replay(queries, ks, arr)
+        st = srv.stats()
+    for r in range(queries.n_rows):
+        k = int(ks[r])
+        _same(ids[r, :k], sc[r, :k], ref_ids[r, :k], ref_sc[r, :k])
+        assert (ids[r, k:] == -1).all() and np.isneginf(sc[r, k:]).all()
+    assert (lat > 0).all()
+    assert st["completed"] == queries.n_rows
+    sel = np.arange(0, queries.n_rows, 12)
+    for k in (10, 50, 100):
+        rows = sel[ks[sel] == k]
+        if len(rows):
+            check_ranked(ids[rows, :k], sc[rows, :k])
+            check_scores(corpus, queries.take_rows(rows), ids[rows, :k], sc[rows, :k], rtol=1e-5)
+
+
+def test_single_request_alone_equals_in_mix(sindi, setup):
+    wl, corpus, queries, idx, ks, ref_ids, ref_sc = setup
+    r = 7
+    a, b = queries.indptr[r], queries.indptr[r + 1]
+    with sindi.Server(idx, max_inflight=1, max_batch=1, k_max=100, gamma=wl.gamma) as srv:
+        ids, sc, _ = srv.wait(srv.submit(queries.indices[a:b], queries.values[a:b], 100), 100)
+        empty_ids, empty_sc, _ = srv.wait(srv.submit(np.zeros(0, np.int32), np.zeros(0, np.float32),
+                                                     10), 10)
+    full_ids, full_sc = idx.search(queries.take_rows([r]), 100, gamma=wl.gamma)
+    _same(ids, sc, full_ids.cpu().numpy()[0], full_sc.cpu().numpy()[0])
+    k = int(ks[r])
+    _same(ids[:k], sc[:k], ref_ids[r, :k], ref_sc[r, :k])
+    # an empty query scores every document 0: the lowest ids, in order
+    assert np.array_equal(empty_ids, np.arange(10)) and (empty_sc == 0).all()
+
+
+def test_server_rejects_invalid_requests(sindi, setup):
+    wl, corpus, queries, idx, ks, ref_ids, ref_sc = setup
+    E = sindi.SindiError
+    with sindi.Server(idx, max_inflight=1, max_batch=8, k_max=50, max_query_nnz=16,
+                      gamma=wl.gamma) as srv:
+        with pytest.raises(E, match="k = 51"):
+            srv.submit([1, 2], [1.0, 1.0], 51)
+        with pytest.raises(E, match="ascending"):
+            srv.submit([2, 1], [1.0, 1.0], 10)
+        with pytest.raises(E, match="out of range"):
+            srv.submit([wl.vocab], [1.0], 10)
+        with pytest.raises(E, match="non-finite"):
+            srv.submit([3], [np.nan], 10)
+        with pytest.raises(E, match="entries"):
+            srv.submit(np.arange(17), np.ones(17), 10)
+        with pytest.raises(E, match="unknown ticket"):
+            srv.wait(12345, 10)
+        q2 = queries.take_rows([0, 1])
+        with pytest.raises(E, match="non-decreasing"):
+            srv.replay(q2, [10, 10], [0.002, 0.001])
+        assert srv.stats()["submitted"] == 0
+    with pytest.raises(E, match="max_batch"):
+        sindi.Server(idx, max_batch=100_000)
+    with pytest.raises(E, match="gamma"):
+        sindi.Server(idx, k_max=600, gamma=500)
