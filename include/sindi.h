@@ -92,6 +92,8 @@ typedef struct {
     int32_t value_dtype;
     double alpha;
     int64_t device_bytes;          /* HBM held by the index                    */
+    int64_t n_slots;               /* posting slots stored: n_postings plus the
+                                      pad entries that align every list to 4   */
 } sindi_index_info;
 
 typedef struct sindi_index sindi_index;
@@ -120,15 +122,19 @@ sindi_status sindi_index_get_info(const sindi_index *idx, sindi_index_info *out)
 /*
  * Copy the device index to host buffers (for checking the layout).
  *   tile_doc   int64 [n_tiles + 1]  first document of each tile
- *   tile_post  int64 [n_tiles + 1]  first posting of each tile
- *   term_off   uint32 [n_tiles * (n_cols + 1)]  list (term j, tile t) occupies
- *              postings tile_post[t] + [term_off[t*(n_cols+1)+j], ...[j+1])
- *   post_doc   uint16 [n_postings]  document id minus tile_doc[t]
- *   post_val   [n_postings] values as stored (4 or 2 bytes each)
+ *   tile_post  int64 [n_tiles + 1]  first posting slot of each tile (multiple of 4)
+ *   term_goff  uint32 [n_tiles * (n_cols + 1)]  for tile t and term j, with
+ *              g = term_goff[t*(n_cols+1) + j]: the list I_{j,t} starts at slot
+ *              tile_post[t] + 4 * (g & 0x3FFFFFFF), holds its postings in
+ *              ascending document order, then (g >> 30) pad entries (value
+ *              0, document id repeated), and the next term's list starts at the
+ *              next 4-slot boundary; entry n_cols holds the tile's slot count / 4
+ *   post_doc   uint16 [n_slots]  document id minus tile_doc[t]
+ *   post_val   [n_slots] values as stored (4 or 2 bytes each)
  * Any pointer may be NULL to skip that array.
  */
 sindi_status sindi_index_export(const sindi_index *idx, int64_t *tile_doc, int64_t *tile_post,
-                                uint32_t *term_off, uint16_t *post_doc, void *post_val);
+                                uint32_t *term_goff, uint16_t *post_doc, void *post_val);
 
 /*
  * Alg. 4: for every query q, the coarse pool = the first gamma documents by

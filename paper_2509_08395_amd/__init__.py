@@ -133,23 +133,53 @@ class Index:
         _lib.check(_lib.load().sindi_index_get_info(self._h, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in inf._fields_}
 
-    def export(self) -> dict:
-        """The device layout copied to host numpy arrays."""
+    def export(self, raw: bool = False) -> dict:
+        """The device layout copied to host numpy arrays.
+
+        raw=True: the stored arrays (lists aligned to 4 slots with pad entries, the
+        encoded group offsets ``term_goff``).  Otherwise the pads are dropped:
+        ``tile_post`` / ``term_off`` [n_tiles, n_cols + 1] are posting offsets of the
+        compacted lists and ``post_doc`` / ``post_val`` hold only real postings."""
         inf = self.info()
-        nt, nc, npost = inf["n_tiles"], inf["n_cols"], inf["n_postings"]
+        nt, nc, nslot = inf["n_tiles"], inf["n_cols"], inf["n_slots"]
         tile_doc = np.empty(nt + 1, np.int64)
         tile_post = np.empty(nt + 1, np.int64)
-        term_off = np.empty(nt * (nc + 1), np.uint32)
-        post_doc = np.empty(max(npost, 1), np.uint16)
+        term_goff = np.empty(nt * (nc + 1), np.uint32)
+        post_doc = np.empty(max(nslot, 1), np.uint16)
         vb = _lib.VALUE_BYTES[inf["value_dtype"]]
-        post_val = np.empty(max(npost, 1) * vb, np.uint8)
+        post_val = np.empty(max(nslot, 1) * vb, np.uint8)
         _lib.check(_lib.load().sindi_index_export(self._h, tile_doc.ctypes.data,
-                                                  tile_post.ctypes.data, term_off.ctypes.data,
+                                                  tile_post.ctypes.data, term_goff.ctypes.data,
                                                   post_doc.ctypes.data, post_val.ctypes.data))
         vt = {4: np.float32, 2: np.uint16}[vb]
-        return {"tile_doc": tile_doc, "tile_post": tile_post,
-                "term_off": term_off.reshape(nt, nc + 1), "post_doc": post_doc[:npost],
-                "post_val": post_val.view(vt)[:npost]}
+        post_doc, post_val = post_doc[:nslot], post_val.view(vt)[:nslot]
+        goff = term_goff.reshape(nt, nc + 1)
+        if raw:
+            return {"tile_doc": tile_doc, "tile_post": tile_post, "term_goff": goff,
+                    "post_doc": post_doc, "post_val": post_val}
+        start = 4 * (goff & 0x3FFFFFFF).astype(np.int64)          # slot offsets in the tile
+        pad = (goff >> 30).astype(np.int64)
+        length = np.diff(start, axis=1) - pad[:, :-1]              # real postings per list
+        term_off = np.zeros((nt, nc + 1), np.int64)
+        np.cumsum(length, axis=1, out=term_off[:, 1:])
+        # slots of the pad entries: (g >> 30) of them after every list's postings
+        pads = pad[:, :-1].ravel()
+        sel = np.nonzero(pads)[0]
+        pad_at = (tile_post[:-1, None] + start[:, :-1]).ravel()[sel] + length.ravel()[sel]
+        pad_n = pads[sel]
+        rank = np.arange(int(pad_n.sum())) - np.repeat(np.cumsum(pad_n) - pad_n, pad_n)
+        keep = np.ones(nslot, bool)
+        keep[np.repeat(pad_at, pad_n) + rank] = False
+        cpost = np.zeros(nt + 1, np.int64)
+        np.cumsum(term_off[:, -1], out=cpost[1:])
+        return {"tile_doc": tile_doc, "tile_post": cpost, "term_off": term_off,
+                "post_doc": post_doc[keep], "post_val": post_val[keep]}
+
+    def term_lengths(self) -> np.ndarray:
+        """Postings per term over all tiles (int64 [n_cols]), pads excluded."""
+        goff = self.export(raw=True)["term_goff"]
+        start = 4 * (goff & 0x3FFFFFFF).astype(np.int64)
+        return (np.diff(start, axis=1) - (goff[:, :-1] >> 30)).sum(axis=0)
 
     def _run(self, fn, queries, k, beta, gamma, batch, cand_cap, sample_tiles, stream, out,
              tile_run=0):

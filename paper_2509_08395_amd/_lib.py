@@ -37,7 +37,8 @@ class SindiIndexInfo(ctypes.Structure):
                 ("n_postings", ctypes.c_int64), ("window", ctypes.c_int64),
                 ("n_windows", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
                 ("tile_max", ctypes.c_int32), ("value_dtype", ctypes.c_int32),
-                ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("n_slots", ctypes.c_int64)]
 
 
 class SindiServerParams(ctypes.Structure):

@@ -135,7 +135,7 @@ constexpr int32_t kDefaultBatch = 1;
 constexpr int32_t kDefaultCandCap = 32768;
 constexpr int32_t kDefaultSampleTiles = 32;
 constexpr int32_t kDefaultGamma = 500;
-constexpr size_t kCandBudget = size_t(2) << 30;  // candidate buffer bytes per pass
+constexpr size_t kCandBudget = size_t(4) << 30;  // candidate buffer bytes per pass
 
 }  // namespace
 
@@ -286,53 +286,70 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
         }
     });
 
-    // Alg. 1 per tile: counts of every (tile, term) list, then offsets
+    // Alg. 1 per tile: counts of every (tile, term) list, then offsets.  Every
+    // list starts on a 4-posting boundary; the slots after its last posting up
+    // to the next boundary are pad entries (value 0, the list's last document),
+    // so the accumulate kernel reads whole 4-posting groups with no end masks.
+    // term_goff holds group offsets relative to the tile's first group, with the
+    // list's pad count in the top two bits.
     const size_t stride = (size_t)nc + 1;
-    std::vector<uint32_t> term_off((size_t)n_tiles * stride, 0u);
+    std::vector<uint32_t> term_goff((size_t)n_tiles * stride, 0u);
     std::vector<int64_t> tile_post((size_t)n_tiles + 1, 0);
-    std::atomic<int> range_bad{0};
-    parallel_for(n_tiles, [&](int64_t lo, int64_t hi) {
-        for (int64_t t = lo; t < hi; ++t) {
-            uint32_t *cnt = term_off.data() + (size_t)t * stride;
-            for (int64_t i = tile_doc[t]; i < tile_doc[t + 1]; ++i)
-                for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e)
-                    if (keep[e]) {
-                        cnt[c->indices[e]]++;
-                        if (p->value_dtype == SINDI_F16 && std::fabs(c->values[e]) > 65504.0f)
-                            range_bad = 1;
-                        if (p->value_dtype == SINDI_BF16 &&
-                            std::isinf(__builtin_bit_cast(float, (uint32_t)to_bf16(c->values[e]) << 16)))
-                            range_bad = 1;
-                    }
-            uint32_t acc = 0;
-            for (int64_t j = 0; j < nc; ++j) {
-                const uint32_t v = cnt[j];
-                cnt[j] = acc;
-                acc += v;
+    std::atomic<int> range_bad{0}, tile_big{0};
+    int64_t n_post = 0;
+    {
+        std::mutex mx;
+        parallel_for(n_tiles, [&](int64_t lo, int64_t hi) {
+            int64_t kept = 0;
+            for (int64_t t = lo; t < hi; ++t) {
+                uint32_t *cnt = term_goff.data() + (size_t)t * stride;
+                for (int64_t i = tile_doc[t]; i < tile_doc[t + 1]; ++i)
+                    for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e)
+                        if (keep[e]) {
+                            cnt[c->indices[e]]++;
+                            ++kept;
+                            if (p->value_dtype == SINDI_F16 && std::fabs(c->values[e]) > 65504.0f)
+                                range_bad = 1;
+                            if (p->value_dtype == SINDI_BF16 &&
+                                std::isinf(__builtin_bit_cast(float, (uint32_t)to_bf16(c->values[e]) << 16)))
+                                range_bad = 1;
+                        }
+                uint64_t g = 0;
+                for (int64_t j = 0; j < nc; ++j) {
+                    const uint32_t n = cnt[j];
+                    const uint32_t pad = (4u - (n & 3u)) & 3u;
+                    cnt[j] = (uint32_t)g | (pad << 30);
+                    g += (n + 3u) / 4u;
+                }
+                if (g > kGoffMask) tile_big = 1;
+                cnt[nc] = (uint32_t)(g & kGoffMask);
+                tile_post[t + 1] = (int64_t)g * 4;
             }
-            cnt[nc] = acc;
-            tile_post[t + 1] = acc;
-        }
-    });
+            std::lock_guard<std::mutex> lock(mx);
+            n_post += kept;
+        });
+    }
     if (range_bad) return fail(SINDI_E_RANGE, "sindi_build: a kept value overflows the storage type");
+    if (tile_big) return fail(SINDI_E_INVALID, "sindi_build: a tile holds 2^32 or more postings");
     for (int64_t t = 0; t < n_tiles; ++t) tile_post[t + 1] += tile_post[t];
-    const int64_t n_post = tile_post[n_tiles];
-    if (n_post >= ((int64_t)1 << 33))
-        return fail(SINDI_E_INVALID, "sindi_build: more than 2^33 index postings");
+    const int64_t n_slots = tile_post[n_tiles];
+    if (n_slots >= ((int64_t)1 << 34))
+        return fail(SINDI_E_INVALID, "sindi_build: more than 2^34 index postings");
     ix->n_post = n_post;
-    const int64_t n_pad = (n_post + 3) / 4 * 4 + 8;
+    ix->n_slots = n_slots;
     const size_t vbytes = p->value_dtype == SINDI_F32 ? 4 : 2;
-    std::vector<uint16_t> post_doc((size_t)n_pad, 0);
-    std::vector<uint8_t> post_val((size_t)n_pad * vbytes, 0);
+    std::vector<uint16_t> post_doc((size_t)n_slots + 4, 0);
+    std::vector<uint8_t> post_val(((size_t)n_slots + 4) * vbytes, 0);
     parallel_for(n_tiles, [&](int64_t lo, int64_t hi) {
-        std::vector<uint32_t> fill(stride);
+        std::vector<uint64_t> fill(stride);
         for (int64_t t = lo; t < hi; ++t) {
-            memcpy(fill.data(), term_off.data() + (size_t)t * stride, stride * sizeof(uint32_t));
+            const uint32_t *go = term_goff.data() + (size_t)t * stride;
+            for (size_t j = 0; j < stride; ++j) fill[j] = 4ull * (go[j] & kGoffMask);
             const int64_t P0 = tile_post[t], d0 = tile_doc[t];
             for (int64_t i = tile_doc[t]; i < tile_doc[t + 1]; ++i)
                 for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e) {
                     if (!keep[e]) continue;
-                    const int64_t pos = P0 + fill[c->indices[e]]++;
+                    const int64_t pos = P0 + (int64_t)fill[c->indices[e]]++;
                     post_doc[pos] = (uint16_t)(i - d0);
                     const float v = c->values[e];
                     if (p->value_dtype == SINDI_F32) memcpy(&post_val[pos * 4], &v, 4);
@@ -341,6 +358,13 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
                         memcpy(&post_val[pos * 2], &h, 2);
                     }
                 }
+            // pads repeat the list's last document (value bits stay 0)
+            for (int64_t j = 0; j < nc; ++j) {
+                const uint32_t pad = go[j] >> 30;
+                if (!pad) continue;
+                const int64_t end = P0 + (int64_t)fill[j];
+                for (uint32_t k = 0; k < pad; ++k) post_doc[end + k] = post_doc[end - 1];
+            }
         }
     });
 
@@ -382,7 +406,7 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     if ((st = up_or_fail(ix->values, c->values, (size_t)c->nnz * 4, "values")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->tile_doc, tile_doc.data(), tile_doc.size() * 8, "tile_doc")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->tile_post, tile_post.data(), tile_post.size() * 8, "tile_post")) != SINDI_OK) return st;
-    if ((st = up_or_fail(ix->term_off, term_off.data(), term_off.size() * 4, "term offsets")) != SINDI_OK) return st;
+    if ((st = up_or_fail(ix->term_goff, term_goff.data(), term_goff.size() * 4, "term offsets")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->post_doc, post_doc.data(), post_doc.size() * 2, "posting ids")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->post_val, post_val.data(), post_val.size(), "posting values")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->term_max, term_max.data(), term_max.size() * 4, "term maxima")) != SINDI_OK) return st;
@@ -656,7 +680,7 @@ sindi::DevIndex sindi_index::dev() const
     d.value_dtype = dtype;
     d.tile_doc = tile_doc.as<int64_t>();
     d.tile_post = tile_post.as<int64_t>();
-    d.term_off = term_off.as<uint32_t>();
+    d.term_goff = term_goff.as<uint32_t>();
     d.post_doc = post_doc.as<uint16_t>();
     d.post_val = post_val.p;
     d.term_max = term_max.as<float>();
@@ -670,7 +694,7 @@ sindi::DevIndex sindi_index::dev() const
 int64_t sindi_index::device_bytes() const
 {
     return (int64_t)(indptr.bytes + indices.bytes + values.bytes + tile_doc.bytes +
-                     tile_post.bytes + term_off.bytes + post_doc.bytes + post_val.bytes +
+                     tile_post.bytes + term_goff.bytes + post_doc.bytes + post_val.bytes +
                      term_max.bytes);
 }
 
@@ -700,6 +724,7 @@ sindi_status sindi_index_get_info(const sindi_index *ix, sindi_index_info *o)
     o->n_cols = ix->n_cols;
     o->nnz = ix->nnz;
     o->n_postings = ix->n_post;
+    o->n_slots = ix->n_slots;
     o->window = ix->window;
     o->n_windows = ix->n_windows;
     o->n_tiles = ix->n_tiles;
@@ -711,15 +736,15 @@ sindi_status sindi_index_get_info(const sindi_index *ix, sindi_index_info *o)
 }
 
 sindi_status sindi_index_export(const sindi_index *ix, int64_t *tile_doc, int64_t *tile_post,
-                                uint32_t *term_off, uint16_t *post_doc, void *post_val)
+                                uint32_t *term_goff, uint16_t *post_doc, void *post_val)
 {
     if (!ix) return fail(SINDI_E_INVALID, "sindi_index_export: null index");
     const size_t vb = ix->dtype == SINDI_F32 ? 4 : 2;
     if (tile_doc) HIP_TRY(hipMemcpy(tile_doc, ix->tile_doc.p, (size_t)(ix->n_tiles + 1) * 8, hipMemcpyDeviceToHost));
     if (tile_post) HIP_TRY(hipMemcpy(tile_post, ix->tile_post.p, (size_t)(ix->n_tiles + 1) * 8, hipMemcpyDeviceToHost));
-    if (term_off) HIP_TRY(hipMemcpy(term_off, ix->term_off.p, (size_t)ix->n_tiles * (ix->n_cols + 1) * 4, hipMemcpyDeviceToHost));
-    if (post_doc && ix->n_post) HIP_TRY(hipMemcpy(post_doc, ix->post_doc.p, (size_t)ix->n_post * 2, hipMemcpyDeviceToHost));
-    if (post_val && ix->n_post) HIP_TRY(hipMemcpy(post_val, ix->post_val.p, (size_t)ix->n_post * vb, hipMemcpyDeviceToHost));
+    if (term_goff) HIP_TRY(hipMemcpy(term_goff, ix->term_goff.p, (size_t)ix->n_tiles * (ix->n_cols + 1) * 4, hipMemcpyDeviceToHost));
+    if (post_doc && ix->n_slots) HIP_TRY(hipMemcpy(post_doc, ix->post_doc.p, (size_t)ix->n_slots * 2, hipMemcpyDeviceToHost));
+    if (post_val && ix->n_slots) HIP_TRY(hipMemcpy(post_val, ix->post_val.p, (size_t)ix->n_slots * vb, hipMemcpyDeviceToHost));
     return SINDI_OK;
 }
 

@@ -16,10 +16,13 @@ struct DevIndex {
     int32_t tile_stride;           // words per query row of the on-chip score tile (>= tile_max, %4 == 0)
     int32_t value_dtype;           // sindi_dtype
     const int64_t *tile_doc;       // [n_tiles + 1] first document of each tile
-    const int64_t *tile_post;      // [n_tiles + 1] first posting of each tile
-    const uint32_t *term_off;      // [n_tiles * (n_cols + 1)] list starts relative to tile_post[t]
-    const uint16_t *post_doc;      // [n_postings + pad] document id - tile_doc[t]
-    const void *post_val;          // [n_postings + pad] value (f32 / f16 / bf16 bits)
+    const int64_t *tile_post;      // [n_tiles + 1] first posting slot of each tile (multiple of 4)
+    const uint32_t *term_goff;     // [n_tiles * (n_cols + 1)] list (term, tile) starts at 4-posting
+                                   // group (term_goff & kGoffMask) of the tile and ends, pads
+                                   // included, where the next term's list starts; top 2 bits:
+                                   // pad entries at its end
+    const uint16_t *post_doc;      // [n_slots] document id - tile_doc[t]; pads repeat the last id
+    const void *post_val;          // [n_slots] value (f32 / f16 / bf16 bits); pads hold 0
     const float *term_max;         // [n_cols] largest |stored value| in the term's lists
     const int64_t *indptr;         // unpruned corpus CSR, [n_docs + 1]
     const int32_t *indices;        // [nnz]
@@ -53,15 +56,19 @@ constexpr int kFinThreads = 256;       // finalize / theta kernels
 constexpr int kGammaMax = 4096;        // largest reorder pool
 constexpr int kQueryHash = 8192;       // rerank hash slots (query nnz <= kQueryHash / 2)
 constexpr int kEntryBlock = 512;       // (query, term) entries merged per pass in the accumulate kernel
-constexpr int kUnroll = 4;             // 4-posting groups in flight per lane
+constexpr int kChunk = 64;             // 4-posting groups per list chunk (one per lane)
+constexpr uint32_t kGoffMask = 0x3FFFFFFFu;
 
 // LDS of one accumulate workgroup: the score rows A[batch][tile_stride], the
 // batch's merged term list (ids + one weight per query) and a region that
-// first holds the merge sort keys, then the per-tile list bounds.
+// first holds the merge sort keys, then the tile's non-empty lists (group
+// start, group count, first chunk, weights).
 inline size_t accumulate_lds_bytes(int batch, int tile_stride)
 {
+    const size_t merge = (size_t)kEntryBlock * 12;
+    const size_t lists = ((size_t)3 * kEntryBlock + 4) * 4 + (size_t)kEntryBlock * batch * 4;
     return (size_t)batch * tile_stride * 4 + (size_t)kEntryBlock * 4 +
-           (size_t)kEntryBlock * batch * 4 + ((size_t)3 * kEntryBlock + 4) * 4;
+           (size_t)kEntryBlock * batch * 4 + (merge > lists ? merge : lists);
 }
 
 // Status codes written per query slot by the finalize kernel.

@@ -43,6 +43,9 @@ __device__ __forceinline__ uint64_t make_key(float s, uint32_t doc)
 __device__ __forceinline__ uint32_t key_doc(uint64_t k) { return 0xFFFFFFFFu - (uint32_t)k; }
 __device__ __forceinline__ float key_score(uint64_t k) { return unord_f32((uint32_t)(k >> 32)); }
 
+// Wave-uniform copy of a value (scalar register).
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -277,6 +280,12 @@ template <> struct Val<0> {  // FP32
         v[2] = __uint_as_float(r.z);
         v[3] = __uint_as_float(r.w);
     }
+    // w * x_p rounded to FP32
+    static __device__ __forceinline__ float prod(const Raw &r, int p, float w)
+    {
+        const uint32_t b = p == 0 ? r.x : (p == 1 ? r.y : (p == 2 ? r.z : r.w));
+        return w * __uint_as_float(b);
+    }
 };
 template <> struct Val<1> {  // FP16
     using Raw = uint2;
@@ -295,6 +304,16 @@ template <> struct Val<1> {  // FP16
         v[2] = h2f(r.y & 0xFFFFu);
         v[3] = h2f(r.y >> 16);
     }
+    // w * x_p rounded to FP32: the FP16 value widens exactly, and a fused
+    // multiply-add with a +0 addend rounds the product once, as a multiply
+    // does (the sign of a zero product is lost, which the integer conversion
+    // that follows ignores); one mixed-precision FMA does both steps.
+    static __device__ __forceinline__ float prod(const Raw &r, int p, float w)
+    {
+        const uint32_t word = p < 2 ? r.x : r.y;
+        const uint32_t bits = (p & 1) ? (word >> 16) : (word & 0xFFFFu);
+        return __builtin_fmaf(w, h2f(bits), 0.0f);
+    }
 };
 template <> struct Val<2> {  // BF16
     using Raw = uint2;
@@ -308,6 +327,11 @@ template <> struct Val<2> {  // BF16
         v[1] = __uint_as_float(r.x & 0xFFFF0000u);
         v[2] = __uint_as_float(r.y << 16);
         v[3] = __uint_as_float(r.y & 0xFFFF0000u);
+    }
+    static __device__ __forceinline__ float prod(const Raw &r, int p, float w)
+    {
+        const uint32_t word = p < 2 ? r.x : r.y;
+        return w * __uint_as_float((p & 1) ? (word & 0xFFFF0000u) : (word << 16));
     }
 };
 
@@ -372,16 +396,18 @@ __device__ __forceinline__ void unpack_pair(uint32_t wlo, uint32_t whi, int32_t 
     h = (int32_t)(whi + (l < 0 ? 1u : 0u));
 }
 
-// One workgroup = a batch of B query slots x a strided set of tiles.  The
+// One workgroup = a batch of B query slots x a contiguous run of tiles.  The
 // batch's (query, term) entries are first merged into one ascending list of
 // distinct terms, each with a weight per query (zero where the query lacks
 // the term), so a list I_{term, tile} shared by several queries of the batch
 // is read once.  Then, for every tile: the score rows (the window's distance
 // array of Sec. 3.3.1, one per query) are cleared in LDS; the tile's lists of
-// all merged terms are laid end to end as aligned 4-posting groups, and each
-// wave sweeps one contiguous share of that range, kUnroll groups per lane in
-// flight; every posting adds w_b * x to query b's score of its document
-// (Alg. 2: product, then accumulate).
+// all merged terms (each padded to whole 4-posting groups with zero values)
+// are cut into chunks of up to 64 groups, and each wave takes a contiguous
+// share of the chunks, several chunks in flight: one group per lane, so a
+// chunk's list, weights and base address are wave-uniform (scalar registers)
+// and a lane only adds its group's offset.  Every posting adds w_b * x to
+// query b's score of its document (Alg. 2: product, then accumulate).
 //
 // Scores are 32-bit fixed point: weights arrive multiplied by the query's
 // power-of-two scale and each product is truncated once to an integer, so
@@ -396,7 +422,7 @@ __device__ __forceinline__ void unpack_pair(uint32_t wlo, uint32_t whi, int32_t 
 // threshold) or every score at or above the query's threshold is appended to
 // its candidate list.
 template <int VT, int B, bool SAMPLE>
-__global__ __launch_bounds__(kAccThreads) void k_accumulate(
+__global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_accumulate(
     DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
     int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
     int64_t cap, int32_t tiles_per_wg)
@@ -404,6 +430,7 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     constexpr int NT = kAccThreads, NW = NT / kWave, EB = kEntryBlock;
     constexpr bool PACK = B >= 2;
     constexpr int NP = PACK ? B / 2 : 1;  // score words per document
+    constexpr int KU = VT == 0 ? 4 : 8;   // chunks in flight per wave
     static_assert(EB == NT, "one merged entry per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = ix.tile_stride;
@@ -414,18 +441,20 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (size_t)EB * B);
     uint64_t *keys = reinterpret_cast<uint64_t *>(region);                 // merge phase
     uint32_t *flag = reinterpret_cast<uint32_t *>(keys + EB);              // merge phase
-    uint32_t *u_gs = reinterpret_cast<uint32_t *>(region);                 // tile phase
-    uint32_t *u_hl = u_gs + EB;
-    uint32_t *gp = u_hl + EB;                                              // EB + 1
+    uint32_t *l_gs = reinterpret_cast<uint32_t *>(region);                 // tile phase
+    uint32_t *l_ng = l_gs + EB;
+    uint32_t *l_cp = l_ng + EB;                                            // EB + 1 (+3)
+    float *l_w = reinterpret_cast<float *>(l_cp + EB + 4);                 // [EB][B]
     __shared__ int64_t s_qa[B];
     __shared__ int32_t s_qpre[B + 1];
     __shared__ int32_t s_slot[B];
     __shared__ float s_qinv[B];
     __shared__ uint32_t s_wsum[NW];
     __shared__ int32_t s_nu;
-    __shared__ uint64_t s_dummy[2];  // target of adds for masked-off postings
+    __shared__ uint32_t s_wl[NW];  // list holding each wave's first chunk
 
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = (int)uni((uint32_t)tid / kWave);  // uniform per wave: keeps chunk bookkeeping scalar
     const int32_t batch = blockIdx.x;
     if (tid == 0) {
         int32_t acc = 0;
@@ -506,7 +535,6 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
 
     if (n_blocks == 1) merge(0);
     const int64_t n_tile_iter = SAMPLE ? n_sample : ix.n_tiles;
-    constexpr int STEP = kWave * kUnroll;
     using Raw = typename Val<VT>::Raw;
 
     // With one merged block, each thread prefetches its term's list bounds of
@@ -522,8 +550,8 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
         const int64_t t = SAMPLE ? (ti * ix.n_tiles / n_sample) : ti;
         const int64_t d0 = ix.tile_doc[t];
         const int32_t len = (int32_t)(ix.tile_doc[t + 1] - d0);
-        const uint64_t P0 = (uint64_t)ix.tile_post[t];
-        const uint32_t *toff = ix.term_off + (size_t)t * (size_t)(ix.n_cols + 1);
+        const uint64_t G0 = (uint64_t)ix.tile_post[t] >> 2;  // first 4-posting group of the tile
+        const uint32_t *toff = ix.term_goff + (size_t)t * (size_t)(ix.n_cols + 1);
 
         int4 *A4 = reinterpret_cast<int4 *>(A);
         for (int i = tid; i < B * T / 4; i += NT) A4[i] = make_int4(0, 0, 0, 0);
@@ -532,30 +560,41 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
         for (int32_t blk = 0; blk < n_blocks; ++blk) {
             if (n_blocks > 1) merge(blk * EB);
             const int32_t nu = s_nu;
-            // list (term, tile) = postings [P0 + lo, P0 + hi); as aligned groups it
-            // starts at group gs and covers positions [lr, hr) counted from 4 * gs
-            uint32_t ng = 0, gs = 0, hl = 0;
+            // list (term, tile) = groups [gs, gs + ng) of the tile, cut into chunks
+            // of kChunk groups; the non-empty lists are compacted in term order
+            // with the index of their first chunk
+            uint32_t gs = 0, ng = 0;
             if (tid < nu) {
                 const int32_t term = u_term[tid];
                 const uint32_t lo = have_pre ? pre_lo : toff[term];
                 const uint32_t hi = have_pre ? pre_hi : toff[term + 1];
-                if (hi > lo) {
-                    const uint64_t a = P0 + lo;
-                    gs = (uint32_t)(a >> 2);
-                    const uint32_t lr = (uint32_t)(a & 3u), hr = lr + (hi - lo);
-                    ng = (hr + 3u) >> 2;
-                    hl = hr | (lr << 30);
+                gs = lo & kGoffMask;
+                ng = (hi & kGoffMask) - gs;
+            }
+            const uint32_t nch = (ng + kChunk - 1) / kChunk;
+            uint32_t total;
+            // low 20 bits: chunks before this list; high bits: non-empty lists before it
+            const uint32_t ex = block_excl_scan<NT>(nch | (nch ? (1u << 20) : 0u), s_wsum, total);
+            // the scan's barriers order these writes after the merge-phase reads
+            if (nch) {
+                const uint32_t li = ex >> 20;
+                l_gs[li] = gs;
+                l_ng[li] = ng;
+                l_cp[li] = ex & 0xFFFFFu;
+#pragma unroll
+                for (int b = 0; b < B; ++b) l_w[li * B + b] = u_w[tid * B + b];
+            }
+            const uint32_t n_list = total >> 20, n_chunk = total & 0xFFFFFu;
+            if (tid == 0) l_cp[n_list] = n_chunk;
+            // wave w takes chunks [n_chunk w / NW, n_chunk (w + 1) / NW)
+            if (nch) {
+                const uint32_t c0l = ex & 0xFFFFFu;
+#pragma unroll
+                for (int w2 = 0; w2 < NW; ++w2) {
+                    const uint32_t cb = (uint32_t)(((uint64_t)n_chunk * (uint32_t)w2) / NW);
+                    if (cb >= c0l && cb < c0l + nch) s_wl[w2] = ex >> 20;
                 }
             }
-            uint32_t total;
-            const uint32_t ex = block_excl_scan<NT>(ng, s_wsum, total);
-            // the scan's barriers order these writes after the merge-phase reads
-            if (tid < nu) {
-                u_gs[tid] = gs;
-                u_hl[tid] = hl;
-            }
-            gp[tid] = ex;
-            if (tid == 0) gp[nu] = total;
             have_pre = false;
             if (n_blocks == 1) {
                 const int64_t tn = ti + 1;
@@ -563,7 +602,7 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
                     have_pre = true;
                     if (tid < nu) {
                         const int64_t t2 = SAMPLE ? (tn * ix.n_tiles / n_sample) : tn;
-                        const uint32_t *toff2 = ix.term_off + (size_t)t2 * (size_t)(ix.n_cols + 1);
+                        const uint32_t *toff2 = ix.term_goff + (size_t)t2 * (size_t)(ix.n_cols + 1);
                         const int32_t term = u_term[tid];
                         pre_lo = toff2[term];
                         pre_hi = toff2[term + 1];
@@ -572,81 +611,97 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
             }
             __syncthreads();
 
-            // this wave's contiguous share of the groups, in whole steps
-            const uint32_t share = ((total + NW - 1) / NW + STEP - 1) / STEP * STEP;
-            const uint32_t g_beg = min(total, (uint32_t)wave * share);
-            const uint32_t g_end = min(total, g_beg + share);
-            int ub = 0;
-            if (g_beg < g_end) {
-                int l = 0, h = nu - 1;
-                while (l < h) {
-                    const int m = (l + h + 1) >> 1;
-                    if (gp[m] <= g_beg) l = m; else h = m - 1;
-                }
-                ub = l;
-            }
-            for (uint32_t base = g_beg; base < g_end; base += STEP) {
-                while (gp[ub + 1] <= base) ++ub;  // wave-uniform
-                uint2 ids[kUnroll];
-                Raw raw[kUnroll];
-                int uu[kUnroll];
-                uint32_t jj[kUnroll];
-                int u = ub;
+            // This wave's contiguous share of the chunks.  One chunk = up to 64
+            // consecutive groups of one list, one group (4 postings) per lane, so a
+            // chunk's list, weights and base address are wave-uniform.  The wave
+            // reads the bounds of 64 consecutive lists at once (one per lane); a
+            // chunk finds its list among them by a ballot over the lists' first
+            // chunks and takes the list's fields by lane broadcast, so KU chunks'
+            // loads leave back to back even where they cross lists.
+            const uint32_t c_beg = (uint32_t)(((uint64_t)n_chunk * (uint32_t)wave) / NW);
+            const uint32_t c_end = (uint32_t)(((uint64_t)n_chunk * (uint32_t)(wave + 1)) / NW);
+            if (c_beg < c_end) {
+                uint32_t lp0 = uni(s_wl[wave]);  // list of chunk c
+                for (uint32_t c = c_beg; c < c_end;) {
+                    const uint32_t lw = lp0 + (uint32_t)lane;
+                    const uint32_t cpn = lw + 1 <= n_list ? l_cp[lw + 1] : 0xFFFFFFFFu;
+                    uint32_t cpl = 0, gsl = 0, ngl = 0;
+                    float wl[B];
 #pragma unroll
-                for (int i = 0; i < kUnroll; ++i) {
-                    const uint32_t vg = base + (uint32_t)(i * kWave + lane);
-                    uu[i] = -1;
-                    if (vg < g_end) {
-                        while (gp[u + 1] <= vg) ++u;
-                        uu[i] = u;
-                        jj[i] = vg - gp[u];
-                        const uint64_t g = (uint64_t)u_gs[u] + jj[i];
-                        ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g];
-                        raw[i] = Val<VT>::load(ix.post_val, g);
+                    for (int b = 0; b < B; ++b) wl[b] = 0.0f;
+                    if (lw < n_list) {
+                        cpl = l_cp[lw];
+                        gsl = l_gs[lw];
+                        ngl = l_ng[lw];
+#pragma unroll
+                        for (int b = 0; b < B; ++b) wl[b] = l_w[lw * B + b];
                     }
-                }
+                    // the window's chunks lie in lists lp0 .. lp0 + 63
+                    const uint32_t c_win = min(c_end, c + (uint32_t)kWave);
+                    for (uint32_t cs = c; cs < c_win; cs += KU) {
+                        uint2 ids[KU];
+                        Raw raw[KU];
+                        uint32_t nl[KU];
+                        int32_t kl[KU];
 #pragma unroll
-                for (int i = 0; i < kUnroll; ++i) {
-                    const int uw = uu[i];
-                    if (uw < 0) continue;
-                    const uint32_t hl2 = u_hl[uw];
-                    const uint32_t lr = hl2 >> 30, hr = hl2 & 0x3FFFFFFFu, r0 = 4u * jj[i];
-                    float w[B];
-                    Weights<B>::read(u_w + (size_t)uw * B, w);
-                    float v[4];
-                    Val<VT>::decode(raw[i], v);
-                    const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16, ids[i].y & 0xFFFFu,
-                                            ids[i].y >> 16};
-                    bool ok[4];
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) ok[p] = r0 + p >= lr && r0 + p < hr;
-                    if (PACK) {
-                        uint64_t *A64 = reinterpret_cast<uint64_t *>(A);
-#pragma unroll
-                        for (int qp = 0; qp < NP; ++qp) {
-                            const float w0 = w[2 * qp], w1 = w[2 * qp + 1];
-                            if (w0 == 0.0f && w1 == 0.0f) continue;
-#pragma unroll
-                            for (int p = 0; p < 4; ++p) {
-                                const int32_t lo = (int32_t)(w0 * v[p]);
-                                const int32_t hi = (int32_t)(w1 * v[p]);
-                                const uint32_t hw = (uint32_t)hi + (uint32_t)(lo >> 31);
-                                uint64_t add = ((uint64_t)hw << 32) | (uint32_t)lo;
-                                uint64_t *dst = A64 + (size_t)qp * T + d4[p];
-                                dst = ok[p] ? dst : s_dummy;
-                                add = ok[p] ? add : 0ull;
-                                __hip_atomic_fetch_add(dst, add, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                        for (int i = 0; i < KU; ++i) {
+                            const uint32_t ci = cs + (uint32_t)i;
+                            nl[i] = 0;
+                            kl[i] = 0;
+                            if (ci < c_win) {
+                                const int32_t k = (int32_t)__popcll(__ballot(cpn <= ci));
+                                kl[i] = k;
+                                const uint32_t j0 = (ci - (uint32_t)__builtin_amdgcn_readlane((int)cpl, k)) *
+                                                    (uint32_t)kChunk;
+                                nl[i] = min((uint32_t)kChunk,
+                                            (uint32_t)__builtin_amdgcn_readlane((int)ngl, k) - j0);
+                                const uint64_t g0 =
+                                    G0 + (uint32_t)__builtin_amdgcn_readlane((int)gsl, k) + j0;
+                                if ((uint32_t)lane < nl[i]) {
+                                    ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g0 + lane];
+                                    raw[i] = reinterpret_cast<const Raw *>(ix.post_val)[g0 + lane];
+                                }
                             }
                         }
-                    } else {
-                        int32_t *A32 = reinterpret_cast<int32_t *>(A);
 #pragma unroll
-                        for (int p = 0; p < 4; ++p) {
-                            int32_t *dst = ok[p] ? A32 + d4[p] : reinterpret_cast<int32_t *>(s_dummy);
-                            lds_add_i32(dst, ok[p] ? (int32_t)(w[0] * v[p]) : 0);
+                        for (int i = 0; i < KU; ++i) {
+                            if ((uint32_t)lane >= nl[i]) continue;
+                            float w[B];
+#pragma unroll
+                            for (int b = 0; b < B; ++b)
+                                w[b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl[b]), kl[i]));
+                            const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16,
+                                                    ids[i].y & 0xFFFFu, ids[i].y >> 16};
+                            if (PACK) {
+                                float v[4];
+                                Val<VT>::decode(raw[i], v);
+                                uint64_t *A64 = reinterpret_cast<uint64_t *>(A);
+#pragma unroll
+                                for (int qp = 0; qp < NP; ++qp) {
+                                    const float w0 = w[2 * qp], w1 = w[2 * qp + 1];
+                                    if (w0 == 0.0f && w1 == 0.0f) continue;
+#pragma unroll
+                                    for (int p = 0; p < 4; ++p) {
+                                        const int32_t lo = (int32_t)(w0 * v[p]);
+                                        const int32_t hi = (int32_t)(w1 * v[p]);
+                                        const uint32_t hw = (uint32_t)hi + (uint32_t)(lo >> 31);
+                                        const uint64_t add = ((uint64_t)hw << 32) | (uint32_t)lo;
+                                        __hip_atomic_fetch_add(A64 + (size_t)qp * T + d4[p], add,
+                                                               __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                                    }
+                                }
+                            } else {
+                                int32_t *A32 = reinterpret_cast<int32_t *>(A);
+#pragma unroll
+                                for (int p = 0; p < 4; ++p)
+                                    lds_add_i32(A32 + d4[p], (int32_t)Val<VT>::prod(raw[i], p, w[0]));
+                            }
                         }
                     }
+                    // list of the next window's first chunk
+                    lp0 += c_win < c_end ? (uint32_t)__popcll(__ballot(cpn <= c_win)) : 0u;
+                    c = c_win;
                 }
             }
             __syncthreads();

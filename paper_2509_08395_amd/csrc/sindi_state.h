@@ -116,13 +116,14 @@ hipError_t timed(int cat, hipStream_t s, F f)
 
 // ------------------------------------------------------------------ index
 struct sindi_index {
-    int64_t n_docs = 0, n_cols = 0, nnz = 0, n_post = 0, window = 0, n_windows = 0, n_tiles = 0;
+    int64_t n_docs = 0, n_cols = 0, nnz = 0, n_post = 0, n_slots = 0, window = 0, n_windows = 0,
+            n_tiles = 0;
     int32_t tile_max = 0, tile_stride = 0, dtype = 0;
     double alpha = 1.0;
     int device = 0;
     int64_t max_lds = 0;
     std::vector<int64_t> h_tile_doc;
-    sindi::DBuf indptr, indices, values, tile_doc, tile_post, term_off, post_doc, post_val,
+    sindi::DBuf indptr, indices, values, tile_doc, tile_post, term_goff, post_doc, post_val,
         term_max;
     std::mutex mu;        // guards ws (the workspace of sindi_search calls)
     sindi::Workspace ws;

@@ -77,6 +77,22 @@ def test_index_layout_is_alg1_bit_exact(sindi, small, dtype):
     # inside every (tile, term) list the documents ascend
     same = (tile_of[1:] == tile_of[:-1]) & (term_of[1:] == term_of[:-1])
     assert (np.diff(doc)[same] > 0).all()
+    # stored form: every list starts on a 4-slot boundary, pads hold value 0 and
+    # repeat the list's last document
+    rx = idx.export(raw=True)
+    goff = rx["term_goff"]
+    assert (rx["tile_post"] % 4 == 0).all() and info["n_slots"] == rx["tile_post"][-1]
+    start = 4 * (goff & 0x3FFFFFFF).astype(np.int64)
+    pad = (goff >> 30).astype(np.int64)
+    length = np.diff(start, axis=1) - pad[:, :-1]
+    assert (length >= 0).all() and (length.sum() == info["n_postings"])
+    assert ((pad[:, :-1] == (-length) % 4)).all() and (pad[:, -1] == 0).all()
+    zero_bits = rx["post_val"].view(np.uint32 if dtype == "f32" else np.uint16)
+    for t in range(nt):
+        for j in np.nonzero(pad[t, :-1])[0][:50]:
+            a = rx["tile_post"][t] + start[t, j] + length[t, j]
+            assert (zero_bits[a:a + pad[t, j]] == 0).all()
+            assert (rx["post_doc"][a:a + pad[t, j]] == rx["post_doc"][a - 1]).all()
     vals = ex["post_val"][order]
     if dtype == "f32":
         assert vals.view(np.uint32).tolist() == ref.val.view(np.uint32).tolist()

@@ -4,7 +4,8 @@ and every returned score is the exact inner product of that document within 1e-5
 import numpy as np
 import pytest
 
-import oracle
+import oracle  # noqa: F401
+import synth
 from parity import check_ranked, check_scores
 from synth.workloads import WORKLOADS
 
@@ -123,7 +124,8 @@ def test_server_rejects_invalid_requests(sindi, setup):
             srv.submit(np.arange(17), np.ones(17), 10)
         with pytest.raises(E, match="unknown ticket"):
             srv.wait(12345, 10)
-        q2 = queries.take_rows([0, 1])
+        q2 = synth.Csr(np.array([0, 1, 2]), np.array([3, 4], np.int32),
+                       np.array([1.0, 2.0], np.float32), wl.vocab)
         with pytest.raises(E, match="non-decreasing"):
             srv.replay(q2, [10, 10], [0.002, 0.001])
         assert srv.stats()["submitted"] == 0
