@@ -66,7 +66,7 @@ typedef struct {
     int32_t value_dtype;     /* sindi_dtype of the stored posting values                 */
     int32_t tile;            /* max documents per on-chip score tile; 0 = library default;
                                 every window is split into equal tiles of at most this
-                                many documents; at most 65536                            */
+                                many documents; at most 16384                            */
 } sindi_build_params;
 
 /* Search parameters (Alg. 4, ApproximateSindiSearch).  Zero fields take defaults. */
@@ -129,7 +129,8 @@ sindi_status sindi_index_get_info(const sindi_index *idx, sindi_index_info *out)
  *              ascending document order, then (g >> 30) pad entries (value
  *              0, document id repeated), and the next term's list starts at the
  *              next 4-slot boundary; entry n_cols holds the tile's slot count / 4
- *   post_doc   uint16 [n_slots]  document id minus tile_doc[t]
+ *   post_doc   uint16 [n_slots]  4 * (document id - tile_doc[t]), the byte offset
+ *              of the document's 32-bit score in an on-chip score row
  *   post_val   [n_slots] values as stored (4 or 2 bytes each)
  * Any pointer may be NULL to skip that array.
  */

@@ -152,7 +152,9 @@ class Index:
                                                   tile_post.ctypes.data, term_goff.ctypes.data,
                                                   post_doc.ctypes.data, post_val.ctypes.data))
         vt = {4: np.float32, 2: np.uint16}[vb]
-        post_doc, post_val = post_doc[:nslot], post_val.view(vt)[:nslot]
+        post_val = post_val.view(vt)[:nslot]
+        # stored: byte offsets of 32-bit score words; returned: tile-local document ids
+        post_doc = post_doc[:nslot] if raw else (post_doc[:nslot] >> 2)
         goff = term_goff.reshape(nt, nc + 1)
         if raw:
             return {"tile_doc": tile_doc, "tile_post": tile_post, "term_goff": goff,

@@ -229,8 +229,8 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     if (p->value_dtype < 0 || p->value_dtype > 2)
         return fail(SINDI_E_INVALID, "sindi_build: unknown value dtype %d", p->value_dtype);
     const int32_t tile_req = p->tile ? p->tile : kDefaultTile;
-    if (tile_req < 1 || tile_req > 65536)
-        return fail(SINDI_E_INVALID, "sindi_build: tile must be in [1, 65536]");
+    if (tile_req < 1 || tile_req > kTileMax)
+        return fail(SINDI_E_INVALID, "sindi_build: tile must be in [1, %d]", kTileMax);
     if (c->n_rows >= (int64_t)0xFFFFFFFF)
         return fail(SINDI_E_INVALID, "sindi_build: too many documents");
     sindi_status st = validate_host_csr(c, "corpus", 0);
@@ -350,7 +350,7 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
                 for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e) {
                     if (!keep[e]) continue;
                     const int64_t pos = P0 + (int64_t)fill[c->indices[e]]++;
-                    post_doc[pos] = (uint16_t)(i - d0);
+                    post_doc[pos] = (uint16_t)((i - d0) * 4);  // byte offset of the score word
                     const float v = c->values[e];
                     if (p->value_dtype == SINDI_F32) memcpy(&post_val[pos * 4], &v, 4);
                     else {

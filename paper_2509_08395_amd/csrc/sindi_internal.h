@@ -21,7 +21,8 @@ struct DevIndex {
                                    // group (term_goff & kGoffMask) of the tile and ends, pads
                                    // included, where the next term's list starts; top 2 bits:
                                    // pad entries at its end
-    const uint16_t *post_doc;      // [n_slots] document id - tile_doc[t]; pads repeat the last id
+    const uint16_t *post_doc;      // [n_slots] 4 * (document id - tile_doc[t]): the byte offset of
+                                   // the document's score word in a row; pads repeat the last one
     const void *post_val;          // [n_slots] value (f32 / f16 / bf16 bits); pads hold 0
     const float *term_max;         // [n_cols] largest |stored value| in the term's lists
     const int64_t *indptr;         // unpruned corpus CSR, [n_docs + 1]
@@ -58,6 +59,7 @@ constexpr int kQueryHash = 8192;       // rerank hash slots (query nnz <= kQuery
 constexpr int kEntryBlock = 512;       // (query, term) entries merged per pass in the accumulate kernel
 constexpr int kChunk = 64;             // 4-posting groups per list chunk (one per lane)
 constexpr uint32_t kGoffMask = 0x3FFFFFFFu;
+constexpr int kTileMax = 16384;        // documents per tile (4 * local id fits 16 bits)
 
 // LDS of one accumulate workgroup: the score rows A[batch][tile_stride], the
 // batch's merged term list (ids + one weight per query) and a region that

@@ -388,6 +388,22 @@ __device__ __forceinline__ void emit_candidates(const float (&sv)[NV], const boo
     }
 }
 
+// Smallest fixed-point sum a with (float)a * qinv >= th, as an int64 (2^31 if
+// no int32 sum reaches th).  (float)a * qinv is non-decreasing in a, so the
+// scores at or above th are exactly the sums at or above this bound.
+__device__ int64_t sum_threshold(float th, float qinv)
+{
+    auto reaches = [&](int64_t a) { return (float)(int32_t)a * qinv >= th; };
+    if (!reaches(INT32_MAX)) return (int64_t)INT32_MAX + 1;
+    int64_t lo = INT32_MIN, hi = INT32_MAX;  // invariant: reaches(hi)
+    if (reaches(lo)) return lo;
+    while (hi - lo > 1) {                     // invariant: !reaches(lo)
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (reaches(mid)) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
 // Decode a pair-packed 64-bit score word into the two 32-bit sums it holds:
 // the word is H * 2^32 + L (exactly, modulo 2^64) with |L|, |H| < 2^31.
 __device__ __forceinline__ void unpack_pair(uint32_t wlo, uint32_t whi, int32_t &l, int32_t &h)
@@ -452,6 +468,8 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     __shared__ uint32_t s_wsum[NW];
     __shared__ int32_t s_nu;
     __shared__ uint32_t s_wl[NW];  // list holding each wave's first chunk
+    __shared__ int32_t s_thr[B];   // per query: smallest sum at or above its threshold
+    __shared__ int32_t s_none[B];  // per query: no sum reaches the threshold
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wave = (int)uni((uint32_t)tid / kWave);  // uniform per wave: keeps chunk bookkeeping scalar
@@ -476,6 +494,13 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
             acc += n;
         }
         s_qpre[B] = acc;
+    }
+    if (!SAMPLE && tid < B) {
+        const int32_t s2 = batch * B + tid;
+        const int64_t a = s2 < n_slots ? sum_threshold(theta[s2], c.qinv[slot_q[s2]])
+                                       : (int64_t)INT32_MAX + 1;
+        s_none[tid] = a > INT32_MAX;
+        s_thr[tid] = a > INT32_MAX ? INT32_MAX : (int32_t)a;
     }
     __syncthreads();
     const int32_t n_e = s_qpre[B];
@@ -670,12 +695,13 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
 #pragma unroll
                             for (int b = 0; b < B; ++b)
                                 w[b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl[b]), kl[i]));
+                            // byte offsets of the documents' 32-bit score words
                             const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16,
                                                     ids[i].y & 0xFFFFu, ids[i].y >> 16};
                             if (PACK) {
                                 float v[4];
                                 Val<VT>::decode(raw[i], v);
-                                uint64_t *A64 = reinterpret_cast<uint64_t *>(A);
+                                unsigned char *A8 = A;
 #pragma unroll
                                 for (int qp = 0; qp < NP; ++qp) {
                                     const float w0 = w[2 * qp], w1 = w[2 * qp + 1];
@@ -686,16 +712,17 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                                         const int32_t hi = (int32_t)(w1 * v[p]);
                                         const uint32_t hw = (uint32_t)hi + (uint32_t)(lo >> 31);
                                         const uint64_t add = ((uint64_t)hw << 32) | (uint32_t)lo;
-                                        __hip_atomic_fetch_add(A64 + (size_t)qp * T + d4[p], add,
-                                                               __ATOMIC_RELAXED,
+                                        uint64_t *dst = reinterpret_cast<uint64_t *>(
+                                            A8 + (size_t)qp * T * 8 + 2u * d4[p]);
+                                        __hip_atomic_fetch_add(dst, add, __ATOMIC_RELAXED,
                                                                __HIP_MEMORY_SCOPE_WORKGROUP);
                                     }
                                 }
                             } else {
-                                int32_t *A32 = reinterpret_cast<int32_t *>(A);
 #pragma unroll
                                 for (int p = 0; p < 4; ++p)
-                                    lds_add_i32(A32 + d4[p], (int32_t)Val<VT>::prod(raw[i], p, w[0]));
+                                    lds_add_i32(reinterpret_cast<int32_t *>(A + d4[p]),
+                                                (int32_t)Val<VT>::prod(raw[i], p, w[0]));
                             }
                         }
                     }
@@ -707,12 +734,16 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
             __syncthreads();
         }
 
-        // ---- read the rows: sample maxima or emit candidates
+        // ---- read the rows: sample maxima or emit every score at or above the
+        // query's threshold, compared as the integer sum against the smallest sum
+        // that reaches the threshold
         if (PACK) {
             const uint64_t *A64 = reinterpret_cast<const uint64_t *>(A);
             for (int qp = 0; qp < NP; ++qp) {
                 const int32_t sl0 = s_slot[2 * qp], sl1 = s_slot[2 * qp + 1];
-                if (sl0 < 0 && sl1 < 0) continue;
+                const bool any0 = sl0 >= 0 && (SAMPLE || !s_none[2 * qp]);
+                const bool any1 = sl1 >= 0 && (SAMPLE || !s_none[2 * qp + 1]);
+                if (!any0 && !any1) continue;
                 const float qi0 = s_qinv[2 * qp], qi1 = s_qinv[2 * qp + 1];
                 const uint64_t *row = A64 + (size_t)qp * T;
                 if (SAMPLE) {
@@ -729,8 +760,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     if (sl1 >= 0)
                         maxima[((size_t)sl1 * n_sample + ti) * NT + tid] = tid < len ? (float)m1 * qi1 : -INFINITY;
                 } else {
-                    const float th0 = sl0 >= 0 ? theta[sl0] : INFINITY;
-                    const float th1 = sl1 >= 0 ? theta[sl1] : INFINITY;
+                    const int32_t th0 = s_thr[2 * qp], th1 = s_thr[2 * qp + 1];
                     for (int base = wave * 128; base < len; base += NW * 128) {
                         const int m0 = base + lane * 2;
                         int4 r = make_int4(0, 0, 0, 0);
@@ -738,11 +768,11 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                         int32_t l0, h0, l1, h1;
                         unpack_pair((uint32_t)r.x, (uint32_t)r.y, l0, h0);
                         unpack_pair((uint32_t)r.z, (uint32_t)r.w, l1, h1);
+                        const bool oa[2] = {any0 && m0 < len && l0 >= th0, any0 && m0 + 1 < len && l1 >= th0};
+                        const bool ob[2] = {any1 && m0 < len && h0 >= th1, any1 && m0 + 1 < len && h1 >= th1};
+                        if (__ballot(oa[0] || oa[1] || ob[0] || ob[1]) == 0) continue;
                         const float a[2] = {(float)l0 * qi0, (float)l1 * qi0};
                         const float b2[2] = {(float)h0 * qi1, (float)h1 * qi1};
-                        const bool oa[2] = {m0 < len && a[0] >= th0, m0 + 1 < len && a[1] >= th0};
-                        const bool ob[2] = {m0 < len && b2[0] >= th1, m0 + 1 < len && b2[1] >= th1};
-                        if (__ballot(oa[0] || oa[1] || ob[0] || ob[1]) == 0) continue;
                         if (sl0 >= 0)
                             emit_candidates<2>(a, oa, d0 + m0, count + sl0, cand + (size_t)sl0 * cap, cap);
                         if (sl1 >= 0)
@@ -753,24 +783,31 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
         } else {
             const int32_t *A32 = reinterpret_cast<const int32_t *>(A);
             const int32_t slot = s_slot[0];
-            if (slot >= 0) {
+            if (slot >= 0 && (SAMPLE || !s_none[0])) {
                 const float qinv = s_qinv[0];
                 if (SAMPLE) {
                     int32_t mx = INT32_MIN;
                     for (int m = tid; m < len; m += NT) mx = max(mx, A32[m]);
                     maxima[((size_t)slot * n_sample + ti) * NT + tid] = tid < len ? (float)mx * qinv : -INFINITY;
                 } else {
-                    const float th = theta[slot];
+                    const int32_t th = s_thr[0];
+                    // words past the tile's documents (up to the row stride) stay 0,
+                    // and lanes past the row end hold INT32_MIN: both need excluding
+                    // only when such a value reaches the threshold
+                    const bool zero_in = th <= 0;
                     for (int base = wave * 256; base < len; base += NW * 256) {
                         const int m0 = base + lane * 4;
-                        int4 r = make_int4(0, 0, 0, 0);
+                        int4 r = make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
                         if (m0 < len) r = *reinterpret_cast<const int4 *>(A32 + m0);
-                        const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv,
-                                             (float)r.z * qinv, (float)r.w * qinv};
+                        const int32_t hi = max(max(r.x, r.y), max(r.z, r.w));
+                        if (__ballot(hi >= th) == 0) continue;  // the common case
                         bool ok[4];
-#pragma unroll
-                        for (int p = 0; p < 4; ++p) ok[p] = (m0 + p < len) && sv[p] >= th;
-                        if (__ballot(ok[0] || ok[1] || ok[2] || ok[3]) == 0) continue;
+                        ok[0] = r.x >= th && (!zero_in || m0 < len);
+                        ok[1] = r.y >= th && (!zero_in || m0 + 1 < len);
+                        ok[2] = r.z >= th && (!zero_in || m0 + 2 < len);
+                        ok[3] = r.w >= th && (!zero_in || m0 + 3 < len);
+                        const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv, (float)r.z * qinv,
+                                             (float)r.w * qinv};
                         emit_candidates<4>(sv, ok, d0 + m0, count + slot, cand + (size_t)slot * cap, cap);
                     }
                 }
@@ -1043,7 +1080,7 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
     const int64_t n_iter = SAMPLE ? n_sample : ix.n_tiles;
     // Contiguous tile ranges per workgroup (see the kernel); the range length
     // keeps the grid at least a few times the chip's resident workgroups.
-    int64_t per = tiles_per_wg > 0 ? tiles_per_wg : 8;
+    int64_t per = tiles_per_wg > 0 ? tiles_per_wg : 32;
     while (per > 1 && n_batches * ((n_iter + per - 1) / per) < 4096) per >>= 1;
     int64_t groups = (n_iter + per - 1) / per;
     if (groups > 65535) {

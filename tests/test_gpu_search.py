@@ -82,6 +82,7 @@ def test_index_layout_is_alg1_bit_exact(sindi, small, dtype):
     rx = idx.export(raw=True)
     goff = rx["term_goff"]
     assert (rx["tile_post"] % 4 == 0).all() and info["n_slots"] == rx["tile_post"][-1]
+    assert (rx["post_doc"] % 4 == 0).all()  # stored as byte offsets of 32-bit score words
     start = 4 * (goff & 0x3FFFFFFF).astype(np.int64)
     pad = (goff >> 30).astype(np.int64)
     length = np.diff(start, axis=1) - pad[:, :-1]
