@@ -141,7 +141,8 @@ constexpr size_t kCandBudget = size_t(4) << 30;  // candidate buffer bytes per p
 
 // Structural check of a host CSR (Def. 1: each row a set of non-zero
 // entries over [0, n_cols); ids strictly ascending; finite values).
-sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max_row)
+sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max_row,
+                               int64_t *longest)
 {
     if (m->n_rows < 0 || m->n_cols < 1 || m->n_cols > INT32_MAX || m->nnz < 0)
         return fail(SINDI_E_INVALID, "%s: bad shape (rows %lld, cols %lld, nnz %lld)", what,
@@ -150,11 +151,13 @@ sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max
         return fail(SINDI_E_INVALID, "%s: null array", what);
     if (m->indptr[0] != 0 || m->indptr[m->n_rows] != m->nnz)
         return fail(SINDI_E_INVALID, "%s: indptr[0] must be 0 and indptr[n_rows] == nnz", what);
-    std::atomic<int64_t> bad_row{-1};
+    std::atomic<int64_t> bad_row{-1}, long_row{0};
     std::atomic<int> bad_kind{0};
     parallel_for(m->n_rows, [&](int64_t lo, int64_t hi) {
+        int64_t lr = 0;
         for (int64_t r = lo; r < hi && bad_row.load(std::memory_order_relaxed) < 0; ++r) {
             const int64_t a = m->indptr[r], b = m->indptr[r + 1];
+            lr = std::max(lr, b - a);
             int kind = 0;
             if (b < a || a < 0 || b > m->nnz) kind = 1;
             else if (max_row > 0 && b - a > max_row) kind = 5;
@@ -170,7 +173,11 @@ sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max
                 if (bad_row.compare_exchange_strong(expect, r)) bad_kind = kind;
             }
         }
+        int64_t cur = long_row.load();
+        while (lr > cur && !long_row.compare_exchange_weak(cur, lr)) {
+        }
     });
+    if (longest) *longest = long_row.load();
     if (bad_row >= 0) {
         static const char *msg[] = {"", "row pointers not monotone", "term id out of range",
                                     "term ids not strictly ascending (duplicate or unsorted)",
@@ -471,7 +478,7 @@ sindi_status reserve_workspace(Workspace &ws, const Plan &pl, int64_t nq, int64_
     HIP_TRY(ws.cn.ensure((size_t)nq * 4 + 4));
     HIP_TRY(ws.qinv.ensure((size_t)nq * 4 + 4));
     HIP_TRY(ws.sabs.ensure(pl.beta < 1.0 ? (size_t)nnz * 8 + 8 : 8));
-    HIP_TRY(ws.err.ensure(4));
+    HIP_TRY(ws.err.ensure(8));
     HIP_TRY(ws.status.ensure((size_t)nq * 4 + 4));
     const int64_t g = std::min<int64_t>(pl.group, std::max<int64_t>(nq, 1));
     HIP_TRY(ws.cand.ensure((size_t)g * pl.cap * 8));
@@ -485,7 +492,7 @@ sindi_status reserve_workspace(Workspace &ws, const Plan &pl, int64_t nq, int64_
 sindi_status enqueue_prep(const sindi_index *ix, Workspace &ws, const Plan &pl,
                           const DevQueries &dq, hipStream_t s)
 {
-    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 1, 0u, s));
+    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 2, 0u, s));
     DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
     HIP_TRY(timed(kProfPrep, s, [&] {
         return launch_query_prep(dq, ix->n_cols, pl.beta, dc, ix->term_max.as<float>(),
@@ -532,7 +539,7 @@ sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
                                    ws.cand.as<uint64_t>(), pl.cap, pl.need, pl.k, pl.rerank,
-                                   out_ids, out_scores, ws.status.as<int32_t>(), s);
+                                   pl.max_qnnz, out_ids, out_scores, ws.status.as<int32_t>(), s);
         }));
     }
     return SINDI_OK;
@@ -566,7 +573,7 @@ sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
                                    ws.cand.as<uint64_t>(), cap_all, pl.need, pl.k, pl.rerank,
-                                   out_ids, out_scores, ws.status.as<int32_t>(), s);
+                                   pl.max_qnnz, out_ids, out_scores, ws.status.as<int32_t>(), s);
         }));
         HIP_TRY(hipStreamSynchronize(s));  // rows[] is pageable host memory
     }
@@ -599,8 +606,11 @@ sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
     if (nq == 0) return SINDI_OK;
     if (qc->on_device && (!qc->indptr || (qc->nnz > 0 && (!qc->indices || !qc->values))))
         return fail(SINDI_E_INVALID, "%s: null query array", fn);
-    if (!qc->on_device && (st = validate_host_csr(qc, "queries", kQueryHash / 2)) != SINDI_OK)
+    int64_t longest = 0;
+    if (!qc->on_device &&
+        (st = validate_host_csr(qc, "queries", kQueryHash / 2, &longest)) != SINDI_OK)
         return st;
+    pl.max_qnnz = (int32_t)longest;
     std::lock_guard<std::mutex> lock(ix->mu);
     Workspace &ws = ix->ws;
     if ((st = reserve_workspace(ws, pl, nq, qc->nnz)) != SINDI_OK) return st;
@@ -623,8 +633,11 @@ sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
     int32_t qerr = 0;
     if (qc->on_device) {
         // device queries: validate before anything reaches the caller's outputs
-        HIP_TRY(hipMemcpyAsync(&qerr, ws.err.p, 4, hipMemcpyDeviceToHost, s));
+        int32_t e2[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(e2, ws.err.p, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        qerr = e2[0];
+        pl.max_qnnz = e2[1];
         if (qerr)
             return fail(SINDI_E_INVALID,
                         "%s: malformed query rows (flags 0x%x: 1 row pointers, 2 term id range, "
@@ -655,8 +668,8 @@ sindi_status check_dev_queries(sindi_index *ix, const sindi_csr *qc, const char 
     HIP_TRY(ws.cw.ensure((size_t)qc->nnz * 4 + 4));
     HIP_TRY(ws.cn.ensure((size_t)qc->n_rows * 4));
     HIP_TRY(ws.qinv.ensure((size_t)qc->n_rows * 4));
-    HIP_TRY(ws.err.ensure(4));
-    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 1, 0u, s));
+    HIP_TRY(ws.err.ensure(8));
+    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 2, 0u, s));
     DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
     HIP_TRY(launch_query_prep(dq, ix->n_cols, 1.0, dc, ix->term_max.as<float>(), nullptr,
                               ws.err.as<int32_t>(), s));

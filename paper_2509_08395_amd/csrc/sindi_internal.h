@@ -77,6 +77,8 @@ inline size_t accumulate_lds_bytes(int batch, int tile_stride)
 enum SlotStatus : int32_t { kSlotOk = 0, kSlotRetry = 1 };
 
 // Kernel launchers (sindi_kernels.hip).  All return hipGetLastError().
+// err_flag[0]: malformed-row bits, err_flag[1]: longest well-formed row (both
+// must be zero on entry).
 hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, DevCoarse c,
                              const float *term_max, double *scratch_abs, int32_t *err_flag,
                              hipStream_t s);
@@ -95,10 +97,12 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 // p[i] = first + i for i in [0, n).
 hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s);
 
+// max_qnnz: bound on the length of every finalized query row (sizes the
+// rerank table; a longer row gets status kSlotRetry).
 hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
                            int32_t n_slots, const uint32_t *count, const uint64_t *cand,
-                           int64_t cap, int32_t need, int32_t k, bool rerank, int64_t *out_ids,
-                           float *out_scores, int32_t *status, hipStream_t s);
+                           int64_t cap, int32_t need, int32_t k, bool rerank, int32_t max_qnnz,
+                           int64_t *out_ids, float *out_scores, int32_t *status, hipStream_t s);
 
 hipError_t launch_score_forward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
                                 int32_t n_cand, float *out, hipStream_t s);

@@ -136,9 +136,9 @@ __device__ K block_select(int64_t n, int64_t r, Load load, uint32_t *hist, int *
 }
 
 // ------------------------------------------------------------------ queries
-// One wave per query row.  Flags malformed rows (err bits: 1 row pointers,
+// One wave per query row.  Flags malformed rows (err[0] bits: 1 row pointers,
 // 2 term id out of range, 4 ids not strictly ascending, 8 non-finite value,
-// 16 more than kQueryHash / 2 entries)
+// 16 more than kQueryHash / 2 entries), keeps the longest row in err[1],
 // and writes the coarse terms: the non-zero entries, cut to the beta-mass
 // subvector when beta < 1 (entries ranked by |q| descending, ties by id;
 // FP64 prefix sums in that order, the first prefix reaching beta * mass),
@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_query_prep(DevQueries q, int64_t n_cols
         }
         return;
     }
+    if (lane == 0) atomicMax(err + 1, (int32_t)(b - a));  // longest row: rerank table size
     int32_t r_keep = 0x7FFFFFFF;  // rank bound of kept entries
     if (beta < 1.0) {
         // rank of every non-zero entry in pi order; |x| placed at its rank
@@ -891,7 +892,7 @@ __device__ __forceinline__ int probe(const QueryHash &h, int32_t id)
     }
 }
 
-__device__ __forceinline__ int hash_lg(int64_t n)
+__host__ __device__ __forceinline__ int hash_lg(int64_t n)
 {
     int lg = 6;
     while ((1ll << lg) < 2 * n) ++lg;
@@ -911,16 +912,27 @@ __device__ __forceinline__ float wave_dot(const DevIndex &ix, const QueryHash &h
     return wave_sum(acc);
 }
 
+// LDS sizes: P = the power of two at or above need keys, a rerank table of
+// 2^hlg slots, hlg = hash_lg of the longest query row of the launch.
+__host__ __device__ inline int32_t pow2_at_least(int32_t n)
+{
+    int32_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
 template <bool RERANK>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     DevIndex ix, DevQueries q, const int32_t *slot_q, const uint32_t *count, const uint64_t *cand,
-    int64_t cap, int32_t need, int32_t k, int64_t *out_ids, float *out_scores, int32_t *status)
+    int64_t cap, int32_t need, int32_t k, int32_t hlg, int64_t *out_ids, float *out_scores,
+    int32_t *status)
 {
     constexpr int NT = kFinThreads, NW = NT / kWave;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint64_t *keys = reinterpret_cast<uint64_t *>(smem);                   // [kGammaMax]
-    int32_t *hid = reinterpret_cast<int32_t *>(keys + kGammaMax);           // [kQueryHash]
-    float *hval = reinterpret_cast<float *>(hid + kQueryHash);              // [kQueryHash]
+    const int32_t P = pow2_at_least(need);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(smem);                   // [P]
+    int32_t *hid = reinterpret_cast<int32_t *>(keys + P);                   // [2^hlg]
+    float *hval = reinterpret_cast<float *>(hid + (1 << hlg));              // [2^hlg]
     __shared__ uint32_t hist[256];
     __shared__ uint32_t s_n;
     __shared__ int s_digit;
@@ -942,14 +954,19 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
         const uint64_t key = cs[i];
         if (key >= kth) {
             const uint32_t p = atomicAdd(&s_n, 1u);
-            if (p < (uint32_t)kGammaMax) keys[p] = key;
+            if (p < (uint32_t)P) keys[p] = key;
         }
     }
     __syncthreads();
 
     if (RERANK) {
         const int64_t qa = q.indptr[row], qb = q.indptr[row + 1];
-        const QueryHash h{hid, hval, nullptr, hash_lg(qb - qa)};
+        const int lg = hash_lg(qb - qa);
+        if (lg > hlg) {  // the launch was sized for shorter rows
+            if (tid == 0) status[row] = kSlotRetry;
+            return;
+        }
+        const QueryHash h{hid, hval, nullptr, lg};
         build_query_hash(q, qa, qb, h);
         for (int ci = wave; ci < need; ci += NW) {
             const uint64_t key = keys[ci];
@@ -959,8 +976,6 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
         __syncthreads();
     }
 
-    int P = 1;
-    while (P < need) P <<= 1;
     for (int i = need + tid; i < P; i += NT) keys[i] = 0ull;
     __syncthreads();
     for (int kk = 2; kk <= P; kk <<= 1) {
@@ -1177,22 +1192,23 @@ hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s)
 
 hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
                            int32_t n_slots, const uint32_t *count, const uint64_t *cand,
-                           int64_t cap, int32_t need, int32_t k, bool rerank, int64_t *out_ids,
-                           float *out_scores, int32_t *status, hipStream_t s)
+                           int64_t cap, int32_t need, int32_t k, bool rerank, int32_t max_qnnz,
+                           int64_t *out_ids, float *out_scores, int32_t *status, hipStream_t s)
 {
     if (n_slots == 0) return hipSuccess;
-    const size_t lds = (size_t)kGammaMax * 8 + (size_t)kQueryHash * 8;
+    const int32_t hlg = rerank ? hash_lg(max_qnnz > 0 ? max_qnnz : 1) : 0;
+    const size_t lds = (size_t)pow2_at_least(need) * 8 + (rerank ? ((size_t)1 << hlg) * 8 : 0);
     hipError_t e;
     if (rerank) {
         e = set_lds(k_finalize<true>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_finalize<true>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
-                           ix, q, slot_q, count, cand, cap, need, k, out_ids, out_scores, status);
+                           ix, q, slot_q, count, cand, cap, need, k, hlg, out_ids, out_scores, status);
     } else {
         e = set_lds(k_finalize<false>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_finalize<false>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
-                           ix, q, slot_q, count, cand, cap, need, k, out_ids, out_scores, status);
+                           ix, q, slot_q, count, cand, cap, need, k, hlg, out_ids, out_scores, status);
     }
     return hipGetLastError();
 }

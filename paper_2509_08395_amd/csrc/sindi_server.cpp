@@ -349,6 +349,7 @@ sindi_status create_impl(const sindi_index *ix, const sindi_server_params *pp, s
     srv->p = p;
     sindi_status st = make_plan(ix, p.max_batch, p.k_max, p.search, true, "sindi_server_create", srv->base);
     if (st != SINDI_OK) return st;
+    srv->base.max_qnnz = p.max_query_nnz;
     srv->group = std::max<int64_t>(
         1, std::min<int64_t>(p.max_batch, p.workspace_bytes / (int64_t)plan_query_bytes(srv->base)));
     srv->base.group = srv->group;

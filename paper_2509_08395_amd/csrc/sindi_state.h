@@ -91,6 +91,7 @@ struct Workspace {
 // The parameters of one search, resolved against the index.
 struct Plan {
     int32_t k = 0, gamma = 0, need = 0, batch = 1, n_sample = 0, tile_run = 0;
+    int32_t max_qnnz = 0;  // bound on every query row's length (rerank table size)
     int64_t cap = 0, rank = 0, n_max = 0, group = 0;
     bool keep_all = true, rerank = true;
     double beta = 1.0;
@@ -138,15 +139,18 @@ namespace sindi {
 sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
                        const sindi_search_params &p, bool rerank, const char *fn, Plan &pl);
 
-// Structural check of a host CSR (Def. 1).  max_row > 0 bounds row length.
-sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max_row);
+// Structural check of a host CSR (Def. 1).  max_row > 0 bounds row length;
+// longest (if not null) receives the longest row.
+sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max_row,
+                               int64_t *longest = nullptr);
 
 // Size ws for nq queries of total nnz under pl (allocations; not async).
 sindi_status reserve_workspace(Workspace &ws, const Plan &pl, int64_t nq, int64_t nnz);
 
 // Enqueue on s the query preparation of rows [0, nq) of dq: beta-mass
 // coarse terms, fixed-point weights and device-side validation, whose flags
-// land in ws.err (0: every row well formed).  No host sync.
+// land in ws.err[0] (0: every row well formed), the longest row in ws.err[1].
+// No host sync.
 sindi_status enqueue_prep(const sindi_index *ix, Workspace &ws, const Plan &pl,
                           const DevQueries &dq, hipStream_t s);
 
