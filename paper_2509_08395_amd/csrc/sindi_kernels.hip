@@ -43,6 +43,16 @@ __device__ __forceinline__ uint64_t make_key(float s, uint32_t doc)
 __device__ __forceinline__ uint32_t key_doc(uint64_t k) { return 0xFFFFFFFFu - (uint32_t)k; }
 __device__ __forceinline__ float key_score(uint64_t k) { return unord_f32((uint32_t)(k >> 32)); }
 
+// A zero vector materialised where it is used (a plain register move the
+// compiler cannot hoist out of the loop and keep live, or spill, at high
+// register pressure).
+__device__ __forceinline__ int4 fresh_zero4()
+{
+    int32_t z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return make_int4(z, z, z, z);
+}
+
 // Wave-uniform copy of a value (scalar register).
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -572,16 +582,18 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     // same pace and share the tiles' lists in L2.
     const int64_t ti_beg = (int64_t)blockIdx.y * tiles_per_wg;
     const int64_t ti_end = min(n_tile_iter, ti_beg + tiles_per_wg);
+    // the score rows start cleared; reading a tile's rows clears them again
+    {
+        int4 *A4 = reinterpret_cast<int4 *>(A);
+        for (int i = tid; i < B * T / 4; i += NT) A4[i] = make_int4(0, 0, 0, 0);
+    }
+    __syncthreads();
     for (int64_t ti = ti_beg; ti < ti_end; ++ti) {
         const int64_t t = SAMPLE ? (ti * ix.n_tiles / n_sample) : ti;
         const int64_t d0 = ix.tile_doc[t];
         const int32_t len = (int32_t)(ix.tile_doc[t + 1] - d0);
         const uint64_t G0 = (uint64_t)ix.tile_post[t] >> 2;  // first 4-posting group of the tile
         const uint32_t *toff = ix.term_goff + (size_t)t * (size_t)(ix.n_cols + 1);
-
-        int4 *A4 = reinterpret_cast<int4 *>(A);
-        for (int i = tid; i < B * T / 4; i += NT) A4[i] = make_int4(0, 0, 0, 0);
-        __syncthreads();
 
         for (int32_t blk = 0; blk < n_blocks; ++blk) {
             if (n_blocks > 1) merge(blk * EB);
@@ -739,18 +751,23 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
         // query's threshold, compared as the integer sum against the smallest sum
         // that reaches the threshold
         if (PACK) {
-            const uint64_t *A64 = reinterpret_cast<const uint64_t *>(A);
+            uint64_t *A64 = reinterpret_cast<uint64_t *>(A);
             for (int qp = 0; qp < NP; ++qp) {
                 const int32_t sl0 = s_slot[2 * qp], sl1 = s_slot[2 * qp + 1];
                 const bool any0 = sl0 >= 0 && (SAMPLE || !s_none[2 * qp]);
                 const bool any1 = sl1 >= 0 && (SAMPLE || !s_none[2 * qp + 1]);
-                if (!any0 && !any1) continue;
+                uint64_t *row = A64 + (size_t)qp * T;
+                if (!any0 && !any1) {
+                    for (int m = tid * 2; m < len; m += NT * 2)
+                        *reinterpret_cast<int4 *>(row + m) = fresh_zero4();
+                    continue;
+                }
                 const float qi0 = s_qinv[2 * qp], qi1 = s_qinv[2 * qp + 1];
-                const uint64_t *row = A64 + (size_t)qp * T;
                 if (SAMPLE) {
                     int32_t m0 = INT32_MIN, m1 = INT32_MIN;
                     for (int m = tid; m < len; m += NT) {
                         const uint64_t wd = row[m];
+                        row[m] = 0ull;
                         int32_t l, h;
                         unpack_pair((uint32_t)wd, (uint32_t)(wd >> 32), l, h);
                         m0 = max(m0, l);
@@ -765,7 +782,10 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     for (int base = wave * 128; base < len; base += NW * 128) {
                         const int m0 = base + lane * 2;
                         int4 r = make_int4(0, 0, 0, 0);
-                        if (m0 < len) r = *reinterpret_cast<const int4 *>(row + m0);
+                        if (m0 < len) {
+                            r = *reinterpret_cast<const int4 *>(row + m0);
+                            *reinterpret_cast<int4 *>(row + m0) = fresh_zero4();
+                        }
                         int32_t l0, h0, l1, h1;
                         unpack_pair((uint32_t)r.x, (uint32_t)r.y, l0, h0);
                         unpack_pair((uint32_t)r.z, (uint32_t)r.w, l1, h1);
@@ -782,13 +802,19 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                 }
             }
         } else {
-            const int32_t *A32 = reinterpret_cast<const int32_t *>(A);
+            int32_t *A32 = reinterpret_cast<int32_t *>(A);
             const int32_t slot = s_slot[0];
-            if (slot >= 0 && (SAMPLE || !s_none[0])) {
+            if (slot < 0 || (!SAMPLE && s_none[0])) {
+                for (int m = tid * 4; m < len; m += NT * 4)
+                    *reinterpret_cast<int4 *>(A32 + m) = fresh_zero4();
+            } else {
                 const float qinv = s_qinv[0];
                 if (SAMPLE) {
                     int32_t mx = INT32_MIN;
-                    for (int m = tid; m < len; m += NT) mx = max(mx, A32[m]);
+                    for (int m = tid; m < len; m += NT) {
+                        mx = max(mx, A32[m]);
+                        A32[m] = 0;
+                    }
                     maxima[((size_t)slot * n_sample + ti) * NT + tid] = tid < len ? (float)mx * qinv : -INFINITY;
                 } else {
                     const int32_t th = s_thr[0];
@@ -799,7 +825,10 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     for (int base = wave * 256; base < len; base += NW * 256) {
                         const int m0 = base + lane * 4;
                         int4 r = make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
-                        if (m0 < len) r = *reinterpret_cast<const int4 *>(A32 + m0);
+                        if (m0 < len) {
+                            r = *reinterpret_cast<const int4 *>(A32 + m0);
+                            *reinterpret_cast<int4 *>(A32 + m0) = fresh_zero4();
+                        }
                         const int32_t hi = max(max(r.x, r.y), max(r.z, r.w));
                         if (__ballot(hi >= th) == 0) continue;  // the common case
                         bool ok[4];
