@@ -520,6 +520,15 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     // Merge entries [e0, e0 + EB) of the batch into u_term / u_w (s_nu terms).
     auto merge = [&](int32_t e0) {
         const int32_t ne = min(EB, n_e - e0);
+        if (B == 1) {  // one query: its coarse terms are already ascending and distinct
+            if (tid < ne) {
+                u_term[tid] = c.ct[s_qa[0] + e0 + tid];
+                u_w[tid] = c.cw[s_qa[0] + e0 + tid];
+            }
+            if (tid == 0) s_nu = ne;
+            __syncthreads();
+            return;
+        }
         int P = 1;
         while (P < ne) P <<= 1;
         if (tid < P) {
@@ -681,25 +690,29 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                         Raw raw[KU];
                         uint32_t nl[KU];
                         int32_t kl[KU];
+                        // Loads are unconditional, so they leave back to back: a lane past
+                        // its chunk's end re-reads the chunk's last group, and a slot past
+                        // the window reads the tile's first group (the tile has groups, or
+                        // it would have no chunks); those lanes add nothing.
 #pragma unroll
                         for (int i = 0; i < KU; ++i) {
                             const uint32_t ci = cs + (uint32_t)i;
-                            nl[i] = 0;
-                            kl[i] = 0;
-                            if (ci < c_win) {
-                                const int32_t k = (int32_t)__popcll(__ballot(cpn <= ci));
-                                kl[i] = k;
-                                const uint32_t j0 = (ci - (uint32_t)__builtin_amdgcn_readlane((int)cpl, k)) *
-                                                    (uint32_t)kChunk;
-                                nl[i] = min((uint32_t)kChunk,
-                                            (uint32_t)__builtin_amdgcn_readlane((int)ngl, k) - j0);
-                                const uint64_t g0 =
-                                    G0 + (uint32_t)__builtin_amdgcn_readlane((int)gsl, k) + j0;
-                                if ((uint32_t)lane < nl[i]) {
-                                    ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g0 + lane];
-                                    raw[i] = reinterpret_cast<const Raw *>(ix.post_val)[g0 + lane];
-                                }
+                            uint64_t g0 = G0;
+                            uint32_t n = 0;
+                            int32_t k = 0;
+                            if (ci < c_win) {  // wave-uniform
+                                k = (int32_t)__popcll(__ballot(cpn <= ci));
+                                const uint32_t j0 =
+                                    (ci - (uint32_t)__builtin_amdgcn_readlane((int)cpl, k)) * (uint32_t)kChunk;
+                                n = min((uint32_t)kChunk,
+                                        (uint32_t)__builtin_amdgcn_readlane((int)ngl, k) - j0);
+                                g0 += (uint32_t)__builtin_amdgcn_readlane((int)gsl, k) + j0;
                             }
+                            kl[i] = k;
+                            nl[i] = n;
+                            const uint32_t off = min((uint32_t)lane, n > 0 ? n - 1 : 0u);
+                            ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g0 + off];
+                            raw[i] = reinterpret_cast<const Raw *>(ix.post_val)[g0 + off];
                         }
 #pragma unroll
                         for (int i = 0; i < KU; ++i) {
