@@ -59,6 +59,48 @@ class Workload:
                                      i0=block << 32)
         return np.cumsum(gaps)
 
+    def plant_positives(self, corpus: synth.Csr, queries: synth.Csr):
+        """One planted positive per query: query b's support copied into a distinct
+        random document p_b, with fresh values 2 x lognormal(0, 0.8).  Returns the new
+        corpus and p (int64 [n_queries])."""
+        nq, nd = queries.n_rows, corpus.n_rows
+        u = synth.uniform_u64(4 * nq + 64, self.seed, synth.STREAM_PLANT)
+        pos, seen = [], set()
+        for x in u:  # distinct documents, first come first served
+            d = int(x % np.uint64(nd))
+            if d not in seen:
+                seen.add(d)
+                pos.append(d)
+            if len(pos) == nq:
+                break
+        pos = np.asarray(pos, np.int64)
+        vals = 2.0 * synth.lognormal_f32(int(queries.nnz), self.seed, synth.STREAM_PLANT,
+                                         i0=1 << 32).astype(np.float32)
+        lens = np.diff(corpus.indptr).astype(np.int64)
+        qlen = np.diff(queries.indptr).astype(np.int64)
+        lens[pos] = qlen
+        indptr = np.zeros(nd + 1, np.int64)
+        np.cumsum(lens, out=indptr[1:])
+        idx = np.empty(int(indptr[-1]), np.int32)
+        val = np.empty(int(indptr[-1]), np.float32)
+        repl = np.zeros(nd, bool)
+        repl[pos] = True
+        keep_rows = np.nonzero(~repl)[0]
+        # untouched rows move as whole blocks
+        src_len = np.diff(corpus.indptr)[keep_rows]
+        src = np.repeat(corpus.indptr[keep_rows], src_len) + (
+            np.arange(int(src_len.sum())) - np.repeat(np.cumsum(src_len) - src_len, src_len))
+        dst = np.repeat(indptr[keep_rows], src_len) + (
+            np.arange(int(src_len.sum())) - np.repeat(np.cumsum(src_len) - src_len, src_len))
+        idx[dst] = corpus.indices[src]
+        val[dst] = corpus.values[src]
+        for b, d in enumerate(pos):
+            a, e = int(queries.indptr[b]), int(queries.indptr[b + 1])
+            o = int(indptr[d])
+            idx[o:o + e - a] = queries.indices[a:e]
+            val[o:o + e - a] = vals[a:e]
+        return synth.Csr(indptr, idx, val, corpus.n_cols), pos
+
     def request_ks(self, n: int, choices=(10, 50, 100), row0: int = 0) -> np.ndarray:
         """k of each serving request, uniform over `choices`."""
         u = synth.uniform_u64(n, self.seed, synth.STREAM_ARRIVALS, i0=(1 << 48) + row0)

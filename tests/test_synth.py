@@ -47,3 +47,24 @@ def test_uniform_length_and_clip():
     d = synth.generate(2000, 1000, nnz=("poisson", 1.0), clip=(1, 512), seed=1)
     assert np.diff(d.indptr).min() == 1
     _check_canonical(d)
+
+
+def test_planted_positives_replace_only_their_rows():
+    from synth.workloads import WORKLOADS
+    wl = WORKLOADS["diff-1m"].scaled(3_000, 12)
+    c, q = wl.corpus(), wl.queries()
+    c2, pos = wl.plant_positives(c, q)
+    assert len(set(pos.tolist())) == q.n_rows and (pos >= 0).all() and (pos < c.n_rows).all()
+    for b, d in enumerate(pos):
+        got = c2.indices[c2.indptr[d]:c2.indptr[d + 1]]
+        assert (got == q.indices[q.indptr[b]:q.indptr[b + 1]]).all()
+        assert (c2.values[c2.indptr[d]:c2.indptr[d + 1]] > 0).all()
+    rest = np.setdiff1d(np.arange(c.n_rows), pos)
+    assert (np.diff(c2.indptr)[rest] == np.diff(c.indptr)[rest]).all()
+    for d in rest[::97]:
+        a, e = c.indptr[d], c.indptr[d + 1]
+        a2 = c2.indptr[d]
+        assert (c2.indices[a2:a2 + e - a] == c.indices[a:e]).all()
+        assert (c2.values[a2:a2 + e - a] == c.values[a:e]).all()
+    c3, pos3 = wl.plant_positives(c, q)  # reproducible
+    assert (pos3 == pos).all() and (c3.values == c2.values).all()
