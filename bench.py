@@ -87,6 +87,10 @@ def main():
                     help="open-loop serving run per arrival rate (0: skip serving)")
     ap.add_argument("--serve-rates", default="",
                     help="comma-separated arrival rates, queries/s (default: the serving workload's)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32 / BF16 posting-storage comparison")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the differentiation (score forward/backward) timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -205,6 +209,10 @@ def main():
         result["latency_p99_ms"] = {str(int(r["offered_qps"])): r["p99_ms"]
                                     for r in result["serving"]["rates"]}
 
+    main_leg = wl.name == "splade-8.8m" and dtype == "f16"
+    if not args.no_diff and main_leg:
+        result["differentiation"] = diff_leg(sindi)
+
     if not args.no_oracle:
         import oracle  # CPU baseline and recall only
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -237,7 +245,85 @@ def main():
             "cpu": _cpu_model()}
         if rec < 0.99:
             result["note"] = f"recall {rec:.4f} below 0.99"
+        if not args.no_precision and main_leg:
+            prec = {"f16": {"qps": result["value"], "ms_per_step": result["ms_per_step"],
+                            "score_pass_ms": result["kernels_ms_per_step"]["accumulate_score"],
+                            "recall_at_k": result["recall_at_k"], "bytes_per_posting": 4}}
+            prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q))
+            result["precision"] = prec
     print(json.dumps(result), flush=True)
+
+
+def precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q, steps=3):
+    """The same search with FP32 and BF16 posting values (each index built on its own):
+    throughput and Recall@k on the same sampled queries."""
+    import torch
+    import oracle
+    out = {}
+    for dt in ("f32", "bf16"):
+        idx = sindi.Index(corpus, alpha=alpha, window=wl.window, value_dtype=dt)
+        ids = torch.empty((n_q, k), dtype=torch.int64, device="cuda")
+        sc = torch.empty((n_q, k), dtype=torch.float32, device="cuda")
+        idx.search(dq, k, gamma=gamma, out=(ids, sc))
+        torch.cuda.synchronize()
+        sindi.profile_enable(True)
+        sindi.profile_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            idx.search(dq, k, gamma=gamma, out=(ids, sc))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        pr = sindi.profile_read(reset=True)
+        sindi.profile_enable(False)
+        rec = oracle.recall_at_k(ids.cpu().numpy()[rsel], truth)
+        out[dt] = {"qps": round(n_q * steps / el, 1), "ms_per_step": round(1e3 * el / steps, 3),
+                   "score_pass_ms": round(pr["accumulate_score"][1] / steps, 3),
+                   "recall_at_k": round(rec, 5), "bytes_per_posting": 6 if dt == "f32" else 4}
+        log(f"precision {dt}: {out[dt]}")
+        idx.close()
+        del idx, ids, sc
+    return out
+
+
+def diff_leg(sindi, steps=5):
+    """Differentiation workload: exact top-100 candidates for 256 queries over 1M documents
+    (vocabulary 250,002), then the pair scores and their gradient w.r.t. query and
+    document values (score forward / backward kernels), timed with HIP events."""
+    import torch
+    from synth.workloads import WORKLOADS
+    wl = WORKLOADS["diff-1m"]
+    corpus, queries = wl.corpus(), wl.queries()
+    corpus, _ = wl.plant_positives(corpus, queries)
+    idx = sindi.Index(corpus, alpha=wl.alpha, window=wl.window)
+    dq = sindi.DeviceCsr.from_host(queries)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ids, _ = idx.search(dq, wl.k, gamma=wl.gamma)
+    search_ms = timed(lambda: idx.search(dq, wl.k, gamma=wl.gamma))
+    fwd_ms = timed(lambda: idx.score(dq, ids))
+    G = torch.randn(ids.shape, device="cuda")
+    gq = torch.zeros(queries.nnz, device="cuda")
+    gx = torch.zeros(corpus.nnz, device="cuda")
+    bwd_ms = timed(lambda: idx.score_backward(dq, ids, G, gq, gx))
+    pairs = ids.numel()
+    rec = {"workload": wl.name, "n_docs": corpus.n_rows, "vocab": wl.vocab,
+           "n_queries": queries.n_rows, "candidates_per_query": wl.k,
+           "exact_search_ms": round(search_ms, 3), "score_forward_ms": round(fwd_ms, 3),
+           "score_backward_ms": round(bwd_ms, 3),
+           "backward_pairs_per_s": round(pairs / (bwd_ms * 1e-3), 1)}
+    log(f"differentiation {rec}")
+    idx.close()
+    return rec
 
 
 def serving_leg(sindi, idx, args):
