@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--workload", default="splade-8.8m")
     ap.add_argument("--value-dtype", default=None, help="posting value storage f32/f16/bf16")
     ap.add_argument("--n-docs", type=int, default=0, help="override corpus size (development)")
+    ap.add_argument("--vocab", type=int, default=0, help="override vocabulary size (sparsity sweeps)")
     ap.add_argument("--queries", type=int, default=0, help="override query count")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
@@ -120,6 +121,9 @@ def main():
     wl = WORKLOADS[args.workload]
     if args.n_docs:
         wl = wl.scaled(args.n_docs)
+    if args.vocab:
+        from dataclasses import replace
+        wl = replace(wl, vocab=args.vocab, name=f"{wl.name}-d{args.vocab}")
     n_q = args.queries or wl.n_queries
     dtype = args.value_dtype or wl.value_dtype
     alpha = wl.alpha if args.alpha is None else args.alpha

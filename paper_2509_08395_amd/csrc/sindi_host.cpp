@@ -538,8 +538,9 @@ sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl
         }));
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
-                                   ws.cand.as<uint64_t>(), pl.cap, pl.need, pl.k, pl.rerank,
-                                   pl.max_qnnz, out_ids, out_scores, ws.status.as<int32_t>(), s);
+                                   ws.cand.as<uint64_t>(), ws.theta.as<float>(), pl.cap, pl.need,
+                                   pl.k, pl.rerank, pl.max_qnnz, out_ids, out_scores,
+                                   ws.status.as<int32_t>(), s);
         }));
     }
     return SINDI_OK;
@@ -572,8 +573,9 @@ sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
         }));
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
-                                   ws.cand.as<uint64_t>(), cap_all, pl.need, pl.k, pl.rerank,
-                                   pl.max_qnnz, out_ids, out_scores, ws.status.as<int32_t>(), s);
+                                   ws.cand.as<uint64_t>(), nullptr, cap_all, pl.need, pl.k,
+                                   pl.rerank, pl.max_qnnz, out_ids, out_scores,
+                                   ws.status.as<int32_t>(), s);
         }));
         HIP_TRY(hipStreamSynchronize(s));  // rows[] is pageable host memory
     }

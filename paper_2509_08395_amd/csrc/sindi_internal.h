@@ -98,11 +98,14 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s);
 
 // max_qnnz: bound on the length of every finalized query row (sizes the
-// rerank table; a longer row gets status kSlotRetry).
+// rerank table; a longer row gets status kSlotRetry).  theta: the thresholds
+// the candidates were emitted with (null: every document was emitted); a
+// threshold <= 0 means the zero sums were left out and are supplied here.
 hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
                            int32_t n_slots, const uint32_t *count, const uint64_t *cand,
-                           int64_t cap, int32_t need, int32_t k, bool rerank, int32_t max_qnnz,
-                           int64_t *out_ids, float *out_scores, int32_t *status, hipStream_t s);
+                           const float *theta, int64_t cap, int32_t need, int32_t k, bool rerank,
+                           int32_t max_qnnz, int64_t *out_ids, float *out_scores, int32_t *status,
+                           hipStream_t s);
 
 hipError_t launch_score_forward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
                                 int32_t n_cand, float *out, hipStream_t s);

@@ -481,6 +481,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     __shared__ uint32_t s_wl[NW];  // list holding each wave's first chunk
     __shared__ int32_t s_thr[B];   // per query: smallest sum at or above its threshold
     __shared__ int32_t s_none[B];  // per query: no sum reaches the threshold
+    __shared__ int32_t s_imp[B];   // per query: threshold <= 0, zero sums left implicit
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wave = (int)uni((uint32_t)tid / kWave);  // uniform per wave: keeps chunk bookkeeping scalar
@@ -512,6 +513,8 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                                        : (int64_t)INT32_MAX + 1;
         s_none[tid] = a > INT32_MAX;
         s_thr[tid] = a > INT32_MAX ? INT32_MAX : (int32_t)a;
+        const float th = s2 < n_slots ? theta[s2] : 1.0f;
+        s_imp[tid] = th <= 0.0f && th != -INFINITY;
     }
     __syncthreads();
     const int32_t n_e = s_qpre[B];
@@ -792,6 +795,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                         maxima[((size_t)sl1 * n_sample + ti) * NT + tid] = tid < len ? (float)m1 * qi1 : -INFINITY;
                 } else {
                     const int32_t th0 = s_thr[2 * qp], th1 = s_thr[2 * qp + 1];
+                    const bool imp0 = s_imp[2 * qp], imp1 = s_imp[2 * qp + 1];
                     for (int base = wave * 128; base < len; base += NW * 128) {
                         const int m0 = base + lane * 2;
                         int4 r = make_int4(0, 0, 0, 0);
@@ -802,8 +806,10 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                         int32_t l0, h0, l1, h1;
                         unpack_pair((uint32_t)r.x, (uint32_t)r.y, l0, h0);
                         unpack_pair((uint32_t)r.z, (uint32_t)r.w, l1, h1);
-                        const bool oa[2] = {any0 && m0 < len && l0 >= th0, any0 && m0 + 1 < len && l1 >= th0};
-                        const bool ob[2] = {any1 && m0 < len && h0 >= th1, any1 && m0 + 1 < len && h1 >= th1};
+                        const bool oa[2] = {any0 && m0 < len && l0 >= th0 && (!imp0 || l0 != 0),
+                                            any0 && m0 + 1 < len && l1 >= th0 && (!imp0 || l1 != 0)};
+                        const bool ob[2] = {any1 && m0 < len && h0 >= th1 && (!imp1 || h0 != 0),
+                                            any1 && m0 + 1 < len && h1 >= th1 && (!imp1 || h1 != 0)};
                         if (__ballot(oa[0] || oa[1] || ob[0] || ob[1]) == 0) continue;
                         const float a[2] = {(float)l0 * qi0, (float)l1 * qi0};
                         const float b2[2] = {(float)h0 * qi1, (float)h1 * qi1};
@@ -831,24 +837,26 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     maxima[((size_t)slot * n_sample + ti) * NT + tid] = tid < len ? (float)mx * qinv : -INFINITY;
                 } else {
                     const int32_t th = s_thr[0];
-                    // words past the tile's documents (up to the row stride) stay 0,
-                    // and lanes past the row end hold INT32_MIN: both need excluding
-                    // only when such a value reaches the threshold
-                    const bool zero_in = th <= 0;
+                    // With a threshold <= 0 the zero sums (most documents) are left out
+                    // and the finalize kernel supplies them in id order; then any nonzero
+                    // word needs a look.  Otherwise a word needs a look if its largest
+                    // sum reaches the threshold.  Lanes past the row end read 0.
+                    const bool imp = s_imp[0];
                     for (int base = wave * 256; base < len; base += NW * 256) {
                         const int m0 = base + lane * 4;
-                        int4 r = make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
+                        int4 r = make_int4(0, 0, 0, 0);
                         if (m0 < len) {
                             r = *reinterpret_cast<const int4 *>(A32 + m0);
                             *reinterpret_cast<int4 *>(A32 + m0) = fresh_zero4();
                         }
-                        const int32_t hi = max(max(r.x, r.y), max(r.z, r.w));
-                        if (__ballot(hi >= th) == 0) continue;  // the common case
+                        const bool look = imp ? ((r.x | r.y | r.z | r.w) != 0)
+                                              : max(max(r.x, r.y), max(r.z, r.w)) >= th;
+                        if (__ballot(look) == 0) continue;  // the common case
                         bool ok[4];
-                        ok[0] = r.x >= th && (!zero_in || m0 < len);
-                        ok[1] = r.y >= th && (!zero_in || m0 + 1 < len);
-                        ok[2] = r.z >= th && (!zero_in || m0 + 2 < len);
-                        ok[3] = r.w >= th && (!zero_in || m0 + 3 < len);
+                        ok[0] = r.x >= th && (!imp || r.x != 0) && m0 < len;
+                        ok[1] = r.y >= th && (!imp || r.y != 0) && m0 + 1 < len;
+                        ok[2] = r.z >= th && (!imp || r.z != 0) && m0 + 2 < len;
+                        ok[3] = r.w >= th && (!imp || r.w != 0) && m0 + 3 < len;
                         const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv, (float)r.z * qinv,
                                              (float)r.w * qinv};
                         emit_candidates<4>(sv, ok, d0 + m0, count + slot, cand + (size_t)slot * cap, cap);
@@ -966,8 +974,8 @@ __host__ __device__ inline int32_t pow2_at_least(int32_t n)
 template <bool RERANK>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     DevIndex ix, DevQueries q, const int32_t *slot_q, const uint32_t *count, const uint64_t *cand,
-    int64_t cap, int32_t need, int32_t k, int32_t hlg, int64_t *out_ids, float *out_scores,
-    int32_t *status)
+    const float *theta, int64_t cap, int32_t need, int32_t k, int32_t hlg, int32_t bm_words,
+    int64_t *out_ids, float *out_scores, int32_t *status)
 {
     constexpr int NT = kFinThreads, NW = NT / kWave;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -975,31 +983,110 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     uint64_t *keys = reinterpret_cast<uint64_t *>(smem);                   // [P]
     int32_t *hid = reinterpret_cast<int32_t *>(keys + P);                   // [2^hlg]
     float *hval = reinterpret_cast<float *>(hid + (1 << hlg));              // [2^hlg]
+    uint32_t *bm = reinterpret_cast<uint32_t *>(hval + (1 << hlg));         // [bm_words]
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t s_n;
+    __shared__ uint32_t s_n, s_wsum[NW];
     __shared__ int s_digit;
     __shared__ int64_t s_need;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int32_t slot = blockIdx.x;
     const int32_t row = slot_q ? slot_q[slot] : slot;
     const uint32_t cnt = count[slot];
-    if ((int64_t)cnt > cap || (int64_t)cnt < (int64_t)need) {
+    const float th = theta ? theta[slot] : -INFINITY;
+    // threshold <= 0: the scoring pass emitted only nonzero sums; every document it did
+    // not emit scores exactly 0
+    const bool imp = th <= 0.0f && th != -INFINITY;
+    if ((int64_t)cnt > cap || (!imp && (int64_t)cnt < (int64_t)need)) {
         if (tid == 0) status[row] = kSlotRetry;
         return;
     }
     const uint64_t *cs = cand + (size_t)slot * (size_t)cap;
-    const uint64_t kth = block_select<uint64_t>(
-        cnt, need, [&](int64_t i) { return cs[i]; }, hist, &s_digit, &s_need);
-    if (tid == 0) s_n = 0;
-    __syncthreads();
-    for (int64_t i = tid; i < cnt; i += NT) {
-        const uint64_t key = cs[i];
-        if (key >= kth) {
-            const uint32_t p = atomicAdd(&s_n, 1u);
-            if (p < (uint32_t)P) keys[p] = key;
-        }
+    constexpr uint32_t kZeroOrd = 0x80000000u;  // ord_f32(0.0f)
+    uint32_t n_pos = (uint32_t)cnt;
+    if (imp) {
+        uint32_t mine = 0;
+        for (int64_t i = tid; i < cnt; i += NT) mine += (uint32_t)(cs[i] >> 32) > kZeroOrd ? 1u : 0u;
+        (void)block_excl_scan<NT>(mine, s_wsum, n_pos);
     }
-    __syncthreads();
+    if (tid == 0) s_n = 0;
+    if (!imp || (int64_t)n_pos >= (int64_t)need) {
+        // the first need candidates (all positive when zeros are implicit)
+        const uint64_t kth = block_select<uint64_t>(
+            cnt, need, [&](int64_t i) { return cs[i]; }, hist, &s_digit, &s_need);
+        __syncthreads();
+        for (int64_t i = tid; i < cnt; i += NT) {
+            const uint64_t key = cs[i];
+            if (key >= kth) {
+                const uint32_t p = atomicAdd(&s_n, 1u);
+                if (p < (uint32_t)P) keys[p] = key;
+            }
+        }
+        __syncthreads();
+    } else {
+        // every positive candidate, then the lowest-id zero-score documents, then (only if
+        // the zeros run out) the best emitted negatives
+        const int64_t zeros_avail = ix.n_docs - (int64_t)cnt;
+        const int64_t zt = min((int64_t)need - n_pos, zeros_avail);
+        const int64_t nt = (int64_t)need - n_pos - zt;
+        const int64_t bound = min(ix.n_docs, zt + (int64_t)cnt);  // the zt-th zero id is below
+        const int32_t words = (int32_t)((bound + 31) / 32);
+        if (nt > (int64_t)cnt - n_pos || words > bm_words) {
+            if (tid == 0) status[row] = kSlotRetry;
+            return;
+        }
+        __syncthreads();
+        for (int64_t i = tid; i < cnt; i += NT) {
+            const uint64_t key = cs[i];
+            if ((uint32_t)(key >> 32) > kZeroOrd) keys[atomicAdd(&s_n, 1u)] = key;
+        }
+        for (int w = tid; w < words; w += NT) bm[w] = 0u;
+        __syncthreads();
+        for (int64_t i = tid; i < cnt; i += NT) {
+            const uint32_t d = key_doc(cs[i]);
+            if ((int64_t)d < bound) atomicOr(&bm[d >> 5], 1u << (d & 31));
+        }
+        __syncthreads();
+        // zero bits in order: each thread owns a run of words
+        const int32_t per = (words + NT - 1) / NT;
+        const int32_t w0 = min(words, tid * per), w1 = min(words, w0 + per);
+        auto free_bits = [&](int32_t w) {
+            uint32_t m = ~bm[w];
+            const int64_t top = bound - (int64_t)w * 32;  // valid bits in this word
+            if (top < 32) m &= (1u << top) - 1u;
+            return m;
+        };
+        uint32_t mine = 0;
+        for (int32_t w = w0; w < w1; ++w) mine += (uint32_t)__popc(free_bits(w));
+        uint32_t tot;
+        uint32_t rank = block_excl_scan<NT>(mine, s_wsum, tot);
+        for (int32_t w = w0; w < w1 && (int64_t)rank < zt; ++w) {
+            uint32_t m = free_bits(w);
+            while (m && (int64_t)rank < zt) {
+                const int b = __ffs(m) - 1;
+                m &= m - 1u;
+                keys[n_pos + rank] = make_key(0.0f, (uint32_t)(w * 32 + b));
+                ++rank;
+            }
+        }
+        if (nt > 0) {
+            // the nt best negatives: non-negative keys map to 0 and rank below them
+            const uint64_t kthn = block_select<uint64_t>(
+                cnt, nt,
+                [&](int64_t i) {
+                    const uint64_t key = cs[i];
+                    return (uint32_t)(key >> 32) < kZeroOrd ? key : 0ull;
+                },
+                hist, &s_digit, &s_need);
+            if (tid == 0) s_n = 0;
+            __syncthreads();
+            for (int64_t i = tid; i < cnt; i += NT) {
+                const uint64_t key = cs[i];
+                if ((uint32_t)(key >> 32) < kZeroOrd && key >= kthn)
+                    keys[n_pos + zt + atomicAdd(&s_n, 1u)] = key;
+            }
+        }
+        __syncthreads();
+    }
 
     if (RERANK) {
         const int64_t qa = q.indptr[row], qb = q.indptr[row + 1];
@@ -1234,23 +1321,30 @@ hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s)
 
 hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
                            int32_t n_slots, const uint32_t *count, const uint64_t *cand,
-                           int64_t cap, int32_t need, int32_t k, bool rerank, int32_t max_qnnz,
-                           int64_t *out_ids, float *out_scores, int32_t *status, hipStream_t s)
+                           const float *theta, int64_t cap, int32_t need, int32_t k, bool rerank,
+                           int32_t max_qnnz, int64_t *out_ids, float *out_scores, int32_t *status,
+                           hipStream_t s)
 {
     if (n_slots == 0) return hipSuccess;
     const int32_t hlg = rerank ? hash_lg(max_qnnz > 0 ? max_qnnz : 1) : 0;
-    const size_t lds = (size_t)pow2_at_least(need) * 8 + (rerank ? ((size_t)1 << hlg) * 8 : 0);
+    // bitmap of candidate ids below need + cap: zero-score documents in id order
+    const int64_t bm = theta ? (need + cap + 31) / 32 : 0;
+    if (bm > (int64_t)1 << 20) return hipErrorInvalidValue;
+    const size_t lds = (size_t)pow2_at_least(need) * 8 + (rerank ? ((size_t)1 << hlg) * 8 : 0) +
+                       (size_t)bm * 4;
     hipError_t e;
     if (rerank) {
         e = set_lds(k_finalize<true>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_finalize<true>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
-                           ix, q, slot_q, count, cand, cap, need, k, hlg, out_ids, out_scores, status);
+                           ix, q, slot_q, count, cand, theta, cap, need, k, hlg, (int32_t)bm,
+                           out_ids, out_scores, status);
     } else {
         e = set_lds(k_finalize<false>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_finalize<false>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
-                           ix, q, slot_q, count, cand, cap, need, k, hlg, out_ids, out_scores, status);
+                           ix, q, slot_q, count, cand, theta, cap, need, k, hlg, (int32_t)bm,
+                           out_ids, out_scores, status);
     }
     return hipGetLastError();
 }

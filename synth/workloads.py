@@ -122,6 +122,16 @@ WORKLOADS = {
     "serving": Workload("serving", 8_800_000, 30_522, ("poisson", 125.0), 20_000,
                         ("uniform", 5, 200), alpha=0.5, window=100_000, gamma=500, k=100,
                         value_dtype="f16", extra={"rates": (2e3, 5e3, 1e4, 2e4, 5e4)}),
+    # Short queries over a large vocabulary (AntSparse shape: BGE-M3, ~40 non-zeros per
+    # document, ~5.8 per query, 250,000 terms); the paper's alpha for it, lambda 50,000.
+    "antsparse-1m": Workload("antsparse-1m", 1_000_000, 250_000, ("poisson", 40.1), 1_000,
+                             ("poisson", 5.8), alpha=0.85, window=50_000, gamma=500, k=50,
+                             value_dtype="f16"),
+    # Uniform sparsity (RANDOM shape): term ids and values uniform, ~120 non-zeros.
+    "random-1m": Workload("random-1m", 1_000_000, 30_000, ("poisson", 120.0), 1_000,
+                          ("poisson", 50.0), alpha=0.5, window=100_000, gamma=500, k=50,
+                          value_dtype="f16", terms=("uniform",), values=("uniform", 0.0, 1.0),
+                          extra={"vocab_sweep": (10_000, 30_000, 100_000)}),
     # Differentiation: multilingual-sized vocabulary, exact top-100 candidates.
     "diff-1m": Workload("diff-1m", 1_000_000, 250_002, ("poisson", 180.0), 256,
                         ("poisson", 40.0), alpha=1.0, window=100_000, gamma=100, k=100,

@@ -75,3 +75,22 @@ def check_same_topk(gpu_ids, ref_ids, ref_scores, tol_abs, pool_margin=None):
 
 def recall(gpu_ids, truth_ids):
     return oracle.recall_at_k(gpu_ids, truth_ids)
+
+
+def kth_tolerance(corpus, queries, ref_ids, rtol):
+    """Per row: twice the FP32 error scale at the reference's last place."""
+    nq = ref_ids.shape[0]
+    last = np.array([r[r >= 0][-1] if (r >= 0).any() else 0 for r in ref_ids])
+    return 2.0 * rtol * score_scale(corpus, queries, np.arange(nq), last)
+
+
+def pool_margin_fn(pool_ids, pool_sc, pruned_corpus, queries, rtol):
+    """Accepts a missing id whose coarse score ties the reference pool's boundary within the
+    coarse tolerance (the approximate method may take either side of such a tie)."""
+    def f(r, d):
+        valid = pool_ids[r] >= 0
+        last, lastid = pool_sc[r][valid][-1], pool_ids[r][valid][-1]
+        c = oracle.pair_scores(pruned_corpus, queries, [r], [d])[0]
+        sc = score_scale(pruned_corpus, queries, [r, r], [d, lastid]).max()
+        return abs(c - last) <= 2 * rtol * sc
+    return f

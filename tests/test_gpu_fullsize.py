@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import check_ranked, check_same_topk, check_scores, score_scale
+from parity import check_ranked, check_same_topk, check_scores, kth_tolerance, pool_margin_fn
 from synth.workloads import WORKLOADS
 
 pytestmark = pytest.mark.gpu
@@ -28,22 +28,6 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _kth_tol(corpus, queries, ref_ids, rtol):
-    nq = ref_ids.shape[0]
-    last = np.array([r[r >= 0][-1] for r in ref_ids])
-    return 2.0 * rtol * score_scale(corpus, queries, np.arange(nq), last)
-
-
-def _pool_margin(pool_ids, pool_sc, cp, qp, rtol):
-    def f(r, d):
-        valid = pool_ids[r] >= 0
-        last, lastid = pool_sc[r][valid][-1], pool_ids[r][valid][-1]
-        c = oracle.pair_scores(cp, qp, [r], [d])[0]
-        sc = score_scale(cp, qp, [r, r], [d, lastid]).max()
-        return abs(c - last) <= 2 * rtol * sc
-    return f
-
-
 def _run(sindi, wl, corpus, queries, dtype):
     idx = sindi.Index(corpus, alpha=wl.alpha, window=wl.window, value_dtype=dtype)
     ids, sc = idx.search(sindi.DeviceCsr.from_host(queries), wl.k, beta=wl.beta, gamma=wl.gamma)
@@ -61,8 +45,8 @@ def test_pruned_1m_every_query(sindi):
     check_ranked(ids, sc)
     check_scores(corpus, queries, ids, sc, rtol=1e-5)
     cp = oracle.apply_mask(corpus, keep)
-    check_same_topk(ids, rid, rsc, _kth_tol(corpus, queries, rid, 1e-5),
-                    pool_margin=_pool_margin(pid, psc, cp, queries, 1e-5))
+    check_same_topk(ids, rid, rsc, kth_tolerance(corpus, queries, rid, 1e-5),
+                    pool_margin=pool_margin_fn(pid, psc, cp, queries, 1e-5))
     truth, _ = oracle.exact_topk(corpus, queries.take_rows(np.arange(0, 1000, 10)), wl.k)
     assert oracle.recall_at_k(ids[::10], truth) >= 0.99
 
@@ -85,7 +69,7 @@ def test_splade_8_8m_sampled_queries(sindi, dtype, coarse_rtol):
     del ref
     cp = oracle.apply_mask(corpus, keep)
     del keep
-    check_same_topk(gi, rid, rsc, _kth_tol(corpus, qs, rid, 1e-5),
-                    pool_margin=_pool_margin(pid, psc, cp, qs, coarse_rtol))
+    check_same_topk(gi, rid, rsc, kth_tolerance(corpus, qs, rid, 1e-5),
+                    pool_margin=pool_margin_fn(pid, psc, cp, qs, coarse_rtol))
     truth, _ = oracle.exact_topk(corpus, qs.take_rows(np.arange(0, 24, 3)), wl.k)
     assert oracle.recall_at_k(gi[::3], truth) >= 0.99

@@ -338,3 +338,32 @@ def test_score_forward_backward_against_oracle(sindi):
     rq, rx = oracle.score_grad(corpus, queries, cand, G.astype(np.float32).astype(np.float64))
     np.testing.assert_allclose(_np(gq), rq, rtol=1e-5, atol=1e-5 * np.abs(rq).max())
     np.testing.assert_allclose(_np(gx), rx, rtol=1e-5, atol=1e-5 * np.abs(rx).max())
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_queries_touching_fewer_documents_than_gamma(sindi, signed):
+    """Most documents score exactly 0 (the query's terms are rare): the pool is every
+    nonzero document, then zero-score documents by ascending id (Alg. 2 keeps filling its
+    heap with zero distances), as in the oracle."""
+    rng = np.random.default_rng(31 + signed)
+    n, vocab = 20_000, 4_000
+    corpus = synth.random_csr(rng, n, vocab, 12, signed=signed, min_nnz=1)
+    # queries over the rarest terms: few documents share any of them
+    cnt = np.bincount(corpus.indices, minlength=vocab)
+    rare = np.argsort(cnt, kind="stable")[:200]
+    rows = []
+    for b in range(24):
+        t = np.sort(rng.choice(rare, size=1 + b % 3, replace=False))
+        v = rng.lognormal(0.0, 0.8, size=t.size) * (rng.choice([-1.0, 1.0], size=t.size) if signed else 1.0)
+        rows.append(dict(zip(t.tolist(), v.astype(np.float32).tolist())))
+    queries = csr_from_dict_rows(dict(enumerate(rows)), len(rows), vocab)
+    idx = sindi.Index(corpus, alpha=0.7, window=5_000, tile=1_000)
+    gamma, k = 300, 40
+    ids, sc = idx.search(queries, k, gamma=gamma, cand_cap=1_000)
+    ids, sc = _np(ids), _np(sc)
+    keep = oracle.mass_prune(corpus, 0.7)
+    ref = oracle.build_index(corpus, 5_000, keep)
+    rid, rsc = oracle.approx_search(ref, corpus, queries, 1.0, gamma, k)
+    check_ranked(ids, sc)
+    check_scores(corpus, queries, ids, sc, rtol=1e-5)
+    assert np.array_equal(ids, rid)
