@@ -92,6 +92,9 @@ def main():
                     help="skip the FP32 / BF16 posting-storage comparison")
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the differentiation (score forward/backward) timing")
+    ap.add_argument("--ablation", action="store_true",
+                    help="only the pruning-rule comparison (MRP / VNP / LP / MRP+LP, Sec. 4.1): "
+                         "Recall@10 and QPS on a 1M-document SPLADE-shaped corpus")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -105,6 +108,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
+
+    if args.ablation:
+        print(json.dumps(ablation(args)), flush=True)
         return
 
     if args.gpus != 1:
@@ -364,6 +371,43 @@ def serving_leg(sindi, idx, args):
     return {"workload": "serving", "query_nnz": "uniform 5..200", "k": "uniform {10, 50, 100}",
             "gamma": wl.gamma, "seconds_per_rate": args.serve_seconds, "max_inflight": 2,
             "max_batch": 512, "rates": out}
+
+
+def ablation(args, n_docs=1_000_000, n_queries=1_000, gamma=100, k=10, steps=3):
+    """The pruning rules of Sec. 4.1 at several strengths on the same corpus and queries."""
+    import torch
+    import oracle
+    import paper_2509_08395_amd as sindi
+    from synth.workloads import WORKLOADS
+    wl = WORKLOADS["splade-8.8m"].scaled(n_docs, n_queries)
+    corpus, queries = wl.corpus(), wl.queries()
+    sel = np.linspace(0, n_queries - 1, 200).astype(np.int64)
+    truth, _ = oracle.exact_topk(corpus, queries.take_rows(sel), k)
+    dq = sindi.DeviceCsr.from_host(queries)
+    grid = ([("mrp", dict(alpha=a)) for a in (0.3, 0.4, 0.5, 0.6, 0.7)] +
+            [("vnp", dict(vn=v)) for v in (8, 14, 22, 30, 45)] +
+            [("lp", dict(list_len=l)) for l in (2_000, 5_000, 10_000, 20_000, 50_000)] +
+            [("mrp+lp", dict(alpha=0.5, list_len=l)) for l in (5_000, 20_000, 50_000)])
+    rows = []
+    for prune, kw in grid:
+        idx = sindi.Index(corpus, window=wl.window, value_dtype="f16", prune=prune, **kw)
+        info = idx.info()
+        ids, _ = idx.search(dq, k, gamma=gamma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ids, _ = idx.search(dq, k, gamma=gamma)
+        torch.cuda.synchronize()
+        qps = n_queries * steps / (time.perf_counter() - t0)
+        rec = oracle.recall_at_k(ids.cpu().numpy()[sel], truth)
+        row = {"prune": prune, **kw, "kept_fraction": round(info["n_postings"] / corpus.nnz, 4),
+               "qps": round(qps, 1), "recall_at_10": round(rec, 4)}
+        log(f"ablation {row}")
+        rows.append(row)
+        idx.close()
+    return {"ablation": "pruning rules (Sec. 4.1)", "workload": wl.name, "n_docs": n_docs,
+            "n_queries": n_queries, "recall_sample": len(sel), "gamma": gamma, "k": k,
+            "value_storage": "f16", "rows": rows}
 
 
 def _cpu_model():

@@ -67,7 +67,23 @@ typedef struct {
     int32_t tile;            /* max documents per on-chip score tile; 0 = library default;
                                 every window is split into equal tiles of at most this
                                 many documents; at most 16384                            */
+    int32_t prune;           /* sindi_prune: which entries of the corpus the lists keep  */
+    int32_t vn;              /* SINDI_PRUNE_VNP: entries kept per document, >= 1         */
+    int64_t list_len;        /* SINDI_PRUNE_LP, _MRP_LP: entries kept per term list, >= 1 */
 } sindi_build_params;
+
+/*
+ * Pruning of the documents before the lists are built (Sec. 4.1).  In every
+ * case only non-zero entries count, and entries are ranked by |x|
+ * descending; ties go to the lower term id within a document and to the
+ * lower document id within a term's list.
+ *   MRP     each document keeps its alpha-mass subvector (Defs. 5-6);
+ *   VNP     each document keeps its vn entries of largest |x|;
+ *   LP      each term's list keeps its list_len entries of largest |x|;
+ *   MRP_LP  MRP first, then LP among the entries MRP kept.
+ */
+typedef enum { SINDI_PRUNE_MRP = 0, SINDI_PRUNE_VNP = 1, SINDI_PRUNE_LP = 2,
+               SINDI_PRUNE_MRP_LP = 3 } sindi_prune;
 
 /* Search parameters (Alg. 4, ApproximateSindiSearch).  Zero fields take defaults. */
 typedef struct {
@@ -94,6 +110,8 @@ typedef struct {
     int64_t device_bytes;          /* HBM held by the index                    */
     int64_t n_slots;               /* posting slots stored: n_postings plus the
                                       pad entries that align every list to 4   */
+    int32_t prune, vn;             /* as built                                 */
+    int64_t list_len;
 } sindi_index_info;
 
 typedef struct sindi_index sindi_index;
@@ -102,8 +120,8 @@ typedef struct sindi_index sindi_index;
  * Build the index of Alg. 3 from a host CSR corpus: every document is cut to
  * its alpha-mass subvector (Defs. 5-6: entries ranked by |x| descending, ties
  * by ascending term id; the shortest prefix whose |x| sum, accumulated in
- * FP64 in that order, reaches alpha times the row's mass), and the kept
- * entries are laid out as the value-storing inverted lists I_{j,w} of Alg. 1
+ * FP64 in that order, reaches alpha times the row's mass), or pruned by the
+ * rule params->prune selects, and the kept entries are laid out as the value-storing inverted lists I_{j,w} of Alg. 1
  * (document ids ascending inside every list), each window further split into
  * score tiles.  The unpruned corpus is kept too, for the exact rerank of
  * Alg. 4.  Both live in device memory owned by the returned handle.

@@ -55,8 +55,11 @@ def _load():
         lib.or_approx_search.argtypes = [I64, I64, P, P, P, P, P, P, I64, P, P, P,
                                          ctypes.c_double, I64, I64, P, P, P, P, ctypes.c_int]
         lib.or_score_grad.argtypes = [P, P, P, P, P, P, I64, I64, P, P, P, P]
+        lib.or_vnp_prune.argtypes = [I64, P, P, P, I64, P, ctypes.c_int]
+        lib.or_lp_prune.argtypes = [I64, I64, P, P, P, I64, P, P]
         for f in (lib.or_exact_topk, lib.or_pair_scores, lib.or_mass_prune, lib.or_build_index,
-                  lib.or_precise_search, lib.or_approx_search, lib.or_score_grad):
+                  lib.or_precise_search, lib.or_approx_search, lib.or_score_grad,
+                  lib.or_vnp_prune, lib.or_lp_prune):
             f.restype = None
         _lib = lib
     return _lib
@@ -106,6 +109,26 @@ def mass_prune(csr, alpha, threads=None):
     p, i, v = _c(csr.indptr, np.int64), _c(csr.indices, np.int32), _c(csr.values, np.float32)
     _load().or_mass_prune(csr.n_rows, _ptr(p), _ptr(i), _ptr(v), float(alpha), _ptr(keep),
                           _threads(threads))
+    return keep
+
+
+def vnp_prune(csr, vn, threads=None):
+    """Keep mask of Vector Number Pruning: the vn entries of largest |x| per row."""
+    keep = np.empty(csr.nnz, dtype=np.uint8)
+    p, i, v = _c(csr.indptr, np.int64), _c(csr.indices, np.int32), _c(csr.values, np.float32)
+    _load().or_vnp_prune(csr.n_rows, _ptr(p), _ptr(i), _ptr(v), int(vn), _ptr(keep),
+                         _threads(threads))
+    return keep
+
+
+def lp_prune(csr, lmax, keep_in=None):
+    """Keep mask of List Pruning: the lmax entries of largest |x| per term list (among
+    the entries keep_in keeps, if given)."""
+    keep = np.empty(csr.nnz, dtype=np.uint8)
+    p, i, v = _c(csr.indptr, np.int64), _c(csr.indices, np.int32), _c(csr.values, np.float32)
+    kin = _c(keep_in, np.uint8) if keep_in is not None else None
+    _load().or_lp_prune(csr.n_rows, int(csr.n_cols), _ptr(p), _ptr(i), _ptr(v), int(lmax),
+                        _ptr(kin) if kin is not None else None, _ptr(keep))
     return keep
 
 

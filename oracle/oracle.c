@@ -17,6 +17,8 @@
  *                      definition of Sec. 5.1
  *   or_pair_scores     Def. 2, one (query, document) pair at a time
  *   or_mass_prune      Defs. 5-6 (mass of a vector, alpha-mass subvector)
+ *   or_vnp_prune       Vector Number Pruning (Sec. 4.1): vn largest |x| per row
+ *   or_lp_prune        List Pruning (Sec. 4.1): l' largest |x| per term list
  *   or_build_index     Alg. 1 (PreciseSindiConstruction) with the window
  *                      partition of Sec. 3.3.1
  *   or_precise_search  Alg. 2 (PreciseSindiSearch)
@@ -248,6 +250,86 @@ void or_mass_prune(int64_t n_rows, const int64_t *ptr, const int32_t *idx, const
             mass_prune_row(idx + ptr[i], val + ptr[i], ptr[i + 1] - ptr[i], alpha, tmp, keep + ptr[i]);
         free(tmp);
     }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Vector Number Pruning (Sec. 4.1): each row keeps the vn non-zero entries  */
+/* of largest |x|; ties in |x| go to the lower term id (the order pi of      */
+/* Def. 6).                                                                  */
+void or_vnp_prune(int64_t n_rows, const int64_t *ptr, const int32_t *idx, const float *val,
+                  int64_t vn, uint8_t *keep, int n_threads)
+{
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+    {
+        int64_t maxn = 1;
+        for (int64_t i = 0; i < n_rows; ++i)
+            if (ptr[i + 1] - ptr[i] > maxn) maxn = ptr[i + 1] - ptr[i];
+        mag_t *tmp = (mag_t *)malloc(sizeof(mag_t) * (size_t)maxn);
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n_rows; ++i) {
+            int64_t n = 0;
+            for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+                keep[e] = 0;
+                if (val[e] == 0.0f) continue;  /* not an entry (Def. 1) */
+                tmp[n].a = fabs((double)val[e]);
+                tmp[n].id = idx[e];
+                tmp[n].pos = e;
+                ++n;
+            }
+            qsort(tmp, (size_t)n, sizeof(mag_t), cmp_mag);
+            for (int64_t t = 0; t < n && t < vn; ++t) keep[tmp[t].pos] = 1;
+        }
+        free(tmp);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* List Pruning (Sec. 4.1): the list of every term keeps its lmax non-zero   */
+/* entries of largest |x|; ties in |x| go to the lower document id.  With    */
+/* keep_in, only entries it keeps take part (the combination of MRP then     */
+/* LP); keep receives the result.                                            */
+typedef struct {
+    double a;
+    int64_t doc;
+    int64_t pos;
+} lent_t;
+static int cmp_lent(const void *x, const void *y)
+{
+    const lent_t *p = (const lent_t *)x, *q = (const lent_t *)y;
+    if (p->a > q->a) return -1;
+    if (p->a < q->a) return 1;
+    return (p->doc > q->doc) - (p->doc < q->doc);
+}
+
+void or_lp_prune(int64_t n_rows, int64_t n_cols, const int64_t *ptr, const int32_t *idx,
+                 const float *val, int64_t lmax, const uint8_t *keep_in, uint8_t *keep)
+{
+    const int64_t nnz = ptr[n_rows];
+    int64_t *cnt = (int64_t *)calloc((size_t)n_cols + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < nnz; ++e) {
+        keep[e] = 0;
+        if (val[e] != 0.0f && (!keep_in || keep_in[e])) cnt[idx[e] + 1]++;
+    }
+    for (int64_t j = 0; j < n_cols; ++j) cnt[j + 1] += cnt[j];
+    lent_t *col = (lent_t *)malloc(sizeof(lent_t) * (size_t)(cnt[n_cols] > 0 ? cnt[n_cols] : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_cols > 0 ? n_cols : 1));
+    for (int64_t j = 0; j < n_cols; ++j) fill[j] = cnt[j];
+    for (int64_t i = 0; i < n_rows; ++i)
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+            if (val[e] == 0.0f || (keep_in && !keep_in[e])) continue;
+            lent_t *c = &col[fill[idx[e]]++];
+            c->a = fabs((double)val[e]);
+            c->doc = i;
+            c->pos = e;
+        }
+    for (int64_t j = 0; j < n_cols; ++j) {
+        const int64_t n = cnt[j + 1] - cnt[j];
+        qsort(col + cnt[j], (size_t)n, sizeof(lent_t), cmp_lent);
+        for (int64_t t = 0; t < n && t < lmax; ++t) keep[col[cnt[j] + t].pos] = 1;
+    }
+    free(fill);
+    free(col);
+    free(cnt);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -106,10 +106,12 @@ def _query_struct(queries):
 class Index:
     """A SINDI index in device memory (Alg. 3: pruned window lists + unpruned corpus)."""
 
-    def __init__(self, corpus, alpha=1.0, window=100_000, value_dtype="f32", tile=0, stream=None):
+    def __init__(self, corpus, alpha=1.0, window=100_000, value_dtype="f32", tile=0, stream=None,
+                 prune="mrp", vn=0, list_len=0):
         lib = _lib.load()
         h = _HostCsr(corpus)
-        params = _lib.SindiBuildParams(float(alpha), int(window), DTYPES[value_dtype], int(tile))
+        params = _lib.SindiBuildParams(float(alpha), int(window), DTYPES[value_dtype], int(tile),
+                                       _lib.PRUNE[prune], int(vn), int(list_len))
         handle = ctypes.c_void_p()
         _lib.check(lib.sindi_build(ctypes.byref(h.struct()), ctypes.byref(params),
                                    _stream(stream), ctypes.byref(handle)))

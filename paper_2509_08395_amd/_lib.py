@@ -23,7 +23,11 @@ class SindiCsr(ctypes.Structure):
 
 class SindiBuildParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("window", ctypes.c_int64),
-                ("value_dtype", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("value_dtype", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("prune", ctypes.c_int32), ("vn", ctypes.c_int32), ("list_len", ctypes.c_int64)]
+
+
+PRUNE = {"mrp": 0, "vnp": 1, "lp": 2, "mrp+lp": 3}
 
 
 class SindiSearchParams(ctypes.Structure):
@@ -38,7 +42,8 @@ class SindiIndexInfo(ctypes.Structure):
                 ("n_windows", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
                 ("tile_max", ctypes.c_int32), ("value_dtype", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_int64),
-                ("n_slots", ctypes.c_int64)]
+                ("n_slots", ctypes.c_int64), ("prune", ctypes.c_int32), ("vn", ctypes.c_int32),
+                ("list_len", ctypes.c_int64)]
 
 
 class SindiServerParams(ctypes.Structure):

@@ -225,13 +225,72 @@ void mass_ratio_row(const int32_t *idx, const float *val, int64_t n, double alph
     for (size_t t = 0; t < r; ++t) keep[order[t]] = 1;
 }
 
+// Vector Number Pruning (Sec. 4.1): the vn non-zero entries of largest |x|,
+// ties to the lower term id (the order of Def. 6).
+void vnp_row(const int32_t *idx, const float *val, int64_t n, int64_t vn,
+             std::vector<int64_t> &order, uint8_t *keep)
+{
+    order.clear();
+    for (int64_t e = 0; e < n; ++e) {
+        keep[e] = 0;
+        if (val[e] != 0.0f) order.push_back(e);
+    }
+    const size_t r = (size_t)std::min<int64_t>(vn, (int64_t)order.size());
+    auto before = [&](int64_t x, int64_t y) {
+        const float ax = std::fabs(val[x]), ay = std::fabs(val[y]);
+        return ax > ay || (ax == ay && idx[x] < idx[y]);
+    };
+    if (r < order.size()) std::nth_element(order.begin(), order.begin() + r, order.end(), before);
+    for (size_t t = 0; t < r; ++t) keep[order[t]] = 1;
+}
+
+// List Pruning (Sec. 4.1): every term's list keeps its lmax non-zero entries
+// of largest |x|, ties to the lower document id; only entries keep already
+// holds take part, and keep is narrowed in place.
+void list_prune(const sindi_csr *c, int64_t lmax, std::vector<uint8_t> &keep)
+{
+    const int64_t nc = c->n_cols, nd = c->n_rows;
+    std::vector<int64_t> start((size_t)nc + 1, 0);
+    for (int64_t e = 0; e < c->nnz; ++e)
+        if (keep[e]) start[(size_t)c->indices[e] + 1]++;
+    for (int64_t j = 0; j < nc; ++j) start[j + 1] += start[j];
+    struct Ent {
+        float a;
+        uint32_t doc;
+        int64_t pos;
+    };
+    std::vector<Ent> ents((size_t)start[nc]);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < nd; ++i)
+            for (int64_t e = c->indptr[i]; e < c->indptr[i + 1]; ++e)
+                if (keep[e]) ents[(size_t)fill[c->indices[e]]++] = {std::fabs(c->values[e]), (uint32_t)i, e};
+    }
+    parallel_for(nc, [&](int64_t lo, int64_t hi) {
+        auto before = [](const Ent &x, const Ent &y) { return x.a > y.a || (x.a == y.a && x.doc < y.doc); };
+        for (int64_t j = lo; j < hi; ++j) {
+            Ent *b = ents.data() + start[j], *e = ents.data() + start[j + 1];
+            if (e - b <= lmax) continue;
+            std::nth_element(b, b + lmax, e, before);
+            for (Ent *x = b + lmax; x < e; ++x) keep[(size_t)x->pos] = 0;
+        }
+    });
+}
+
 sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStream_t s,
                         sindi_index **out)
 {
     if (!c || !p || !out) return fail(SINDI_E_INVALID, "sindi_build: null argument");
     if (c->on_device) return fail(SINDI_E_INVALID, "sindi_build: corpus must be host memory");
-    if (!(p->alpha > 0.0 && p->alpha <= 1.0))
+    if (p->prune < SINDI_PRUNE_MRP || p->prune > SINDI_PRUNE_MRP_LP)
+        return fail(SINDI_E_INVALID, "sindi_build: unknown pruning rule %d", p->prune);
+    const bool use_mrp = p->prune == SINDI_PRUNE_MRP || p->prune == SINDI_PRUNE_MRP_LP;
+    const bool use_lp = p->prune == SINDI_PRUNE_LP || p->prune == SINDI_PRUNE_MRP_LP;
+    if (use_mrp && !(p->alpha > 0.0 && p->alpha <= 1.0))
         return fail(SINDI_E_INVALID, "sindi_build: alpha must be in (0, 1], got %g", p->alpha);
+    if (p->prune == SINDI_PRUNE_VNP && p->vn < 1)
+        return fail(SINDI_E_INVALID, "sindi_build: vn must be >= 1");
+    if (use_lp && p->list_len < 1) return fail(SINDI_E_INVALID, "sindi_build: list_len must be >= 1");
     if (p->window < 1) return fail(SINDI_E_INVALID, "sindi_build: window must be >= 1");
     if (p->value_dtype < 0 || p->value_dtype > 2)
         return fail(SINDI_E_INVALID, "sindi_build: unknown value dtype %d", p->value_dtype);
@@ -255,6 +314,9 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     ix->n_cols = nc;
     ix->nnz = c->nnz;
     ix->alpha = p->alpha;
+    ix->prune = p->prune;
+    ix->vn = p->vn;
+    ix->list_len = p->list_len;
     ix->window = p->window;
     ix->dtype = p->value_dtype;
     ix->n_windows = nd ? (nd + p->window - 1) / p->window : 0;
@@ -282,16 +344,21 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
         return fail(SINDI_E_INVALID, "sindi_build: tile of %d documents exceeds on-chip memory",
                     tmax);
 
-    // Alg. 3 line 3: alpha-mass subvector of every document
+    // Alg. 3 line 3: alpha-mass subvector of every document (or the rule chosen)
     std::vector<uint8_t> keep((size_t)c->nnz);
     parallel_for(nd, [&](int64_t lo, int64_t hi) {
         std::vector<int64_t> order;
         for (int64_t r = lo; r < hi; ++r) {
-            const int64_t a = c->indptr[r];
-            mass_ratio_row(c->indices + a, c->values + a, c->indptr[r + 1] - a, p->alpha, order,
-                           keep.data() + a);
+            const int64_t a = c->indptr[r], n = c->indptr[r + 1] - a;
+            if (use_mrp)
+                mass_ratio_row(c->indices + a, c->values + a, n, p->alpha, order, keep.data() + a);
+            else if (p->prune == SINDI_PRUNE_VNP)
+                vnp_row(c->indices + a, c->values + a, n, p->vn, order, keep.data() + a);
+            else
+                for (int64_t e = 0; e < n; ++e) keep[a + e] = c->values[a + e] != 0.0f;
         }
     });
+    if (use_lp) list_prune(c, p->list_len, keep);
 
     // Alg. 1 per tile: counts of every (tile, term) list, then offsets.  Every
     // list starts on a 4-posting boundary; the slots after its last posting up
@@ -740,6 +807,9 @@ sindi_status sindi_index_get_info(const sindi_index *ix, sindi_index_info *o)
     o->nnz = ix->nnz;
     o->n_postings = ix->n_post;
     o->n_slots = ix->n_slots;
+    o->prune = ix->prune;
+    o->vn = ix->vn;
+    o->list_len = ix->list_len;
     o->window = ix->window;
     o->n_windows = ix->n_windows;
     o->n_tiles = ix->n_tiles;

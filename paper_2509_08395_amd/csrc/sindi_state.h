@@ -119,7 +119,8 @@ hipError_t timed(int cat, hipStream_t s, F f)
 struct sindi_index {
     int64_t n_docs = 0, n_cols = 0, nnz = 0, n_post = 0, n_slots = 0, window = 0, n_windows = 0,
             n_tiles = 0;
-    int32_t tile_max = 0, tile_stride = 0, dtype = 0;
+    int32_t tile_max = 0, tile_stride = 0, dtype = 0, prune = 0, vn = 0;
+    int64_t list_len = 0;
     double alpha = 1.0;
     int device = 0;
     int64_t max_lds = 0;

@@ -136,3 +136,14 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(c, "size")] == ctypes.sizeof(py), c
         for f, _ in py._fields_:
             assert got[(c, f)] == getattr(py, f).offset, (c, f)
+
+
+@pytest.mark.parametrize("prune,vn,list_len", [(7, 0, 0), (-1, 0, 0), (1, 0, 0), (2, 0, 0), (3, 5, 0)])
+def test_build_rejects_bad_pruning_parameters(prune, vn, list_len):
+    from paper_2509_08395_amd import _lib
+    lib = _lib.load()
+    s, keep = _csr_struct([0, 1], [1], [1.0], n_cols=5)
+    p = _lib.SindiBuildParams(0.5, 10, 0, 0, prune, vn, list_len)
+    h = ctypes.c_void_p()
+    assert lib.sindi_build(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(h)) == _lib.SINDI_E_INVALID
+    assert not h.value

@@ -5,7 +5,7 @@ import pytest
 import oracle
 import synth
 from conftest import csr_from_dict_rows, load_golden
-from parity import check_ranked, check_same_topk, check_scores, score_scale
+from parity import pool_margin_fn, check_ranked, check_same_topk, check_scores, score_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -367,3 +367,41 @@ def test_queries_touching_fewer_documents_than_gamma(sindi, signed):
     check_ranked(ids, sc)
     check_scores(corpus, queries, ids, sc, rtol=1e-5)
     assert np.array_equal(ids, rid)
+
+
+
+@pytest.mark.parametrize("prune,kw", [("vnp", dict(vn=20)), ("lp", dict(list_len=300)),
+                                      ("mrp+lp", dict(alpha=0.5, list_len=200))])
+def test_pruning_rules_layout_and_search(sindi, small, prune, kw):
+    """VNP, LP and MRP-then-LP (Sec. 4.1): the lists hold exactly the oracle's kept entries
+    (Alg. 1 order, values bit-exact) and the search matches the oracle's Alg. 4 over them."""
+    corpus, queries = small
+    idx = sindi.Index(corpus, window=WINDOW, tile=TILE, prune=prune, **kw)
+    if prune == "vnp":
+        keep = oracle.vnp_prune(corpus, kw["vn"])
+    elif prune == "lp":
+        keep = oracle.lp_prune(corpus, kw["list_len"])
+    else:
+        keep = oracle.lp_prune(corpus, kw["list_len"], keep_in=oracle.mass_prune(corpus, kw["alpha"]))
+    info = idx.info()
+    assert info["n_postings"] == int(keep.sum()) and info["prune"] == sindi._lib.PRUNE[prune]
+    ex = idx.export()
+    ref = oracle.build_index(corpus, WINDOW, keep)
+    tile_doc, tile_post, term_off = ex["tile_doc"], ex["tile_post"], ex["term_off"]
+    nt = tile_doc.shape[0] - 1
+    tile_of = np.repeat(np.arange(nt), np.diff(tile_post))
+    term_of = np.concatenate([np.repeat(np.arange(VOCAB), np.diff(term_off[t])) for t in range(nt)])
+    doc = ex["post_doc"].astype(np.int64) + tile_doc[tile_of]
+    order = np.lexsort((doc, doc // WINDOW, term_of))
+    assert (doc[order] == ref.doc.astype(np.int64)).all()
+    assert (term_of[order] == np.repeat(np.arange(VOCAB), np.diff(ref.ptr[::ref.sigma]))).all()
+    assert ex["post_val"][order].view(np.uint32).tolist() == ref.val.view(np.uint32).tolist()
+    gamma, k = 200, 20
+    ids, sc = idx.search(queries, k, gamma=gamma)
+    ids, sc = _np(ids), _np(sc)
+    rid, rsc, pid, psc = oracle.approx_search(ref, corpus, queries, 1.0, gamma, k, want_pool=True)
+    check_ranked(ids, sc)
+    check_scores(corpus, queries, ids, sc, rtol=1e-5)
+    cp = oracle.apply_mask(corpus, keep)
+    check_same_topk(ids, rid, rsc, _tol_kth(corpus, queries, rid, rsc, 1e-5),
+                    pool_margin=pool_margin_fn(pid, psc, cp, queries, 1e-5))

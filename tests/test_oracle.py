@@ -345,3 +345,76 @@ def test_score_grad_matches_finite_differences():
             M[d, t] -= h
             fd = (loss(Dq, P) - loss(Dq, M)) / (2 * h)
             assert gx[e] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+# ------------------------------------------------------------------ VNP and LP (Sec. 4.1)
+def _transpose(csr):
+    """The CSR of the transpose (rows = terms, column ids = document ids) and, for every
+    entry of it, the position of the same entry in csr."""
+    import synth
+    rows = np.repeat(np.arange(csr.n_rows), np.diff(csr.indptr))
+    order = np.lexsort((rows, csr.indices))
+    counts = np.bincount(csr.indices, minlength=csr.n_cols)
+    indptr = np.zeros(csr.n_cols + 1, np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    t = synth.Csr(indptr, rows[order].astype(np.int32), csr.values[order].copy(), csr.n_rows)
+    return t, order
+
+
+def _vnp_invariants(csr, vn, keep):
+    for r in range(csr.n_rows):
+        a, b = csr.indptr[r], csr.indptr[r + 1]
+        k, v, ids = keep[a:b].astype(bool), np.abs(csr.values[a:b].astype(np.float64)), csr.indices[a:b]
+        nz = v > 0
+        assert k.sum() == min(vn, nz.sum())
+        assert not (k & ~nz).any()
+        if k.any() and (nz & ~k).any():
+            lo_kept, hi_drop = v[k].min(), v[nz & ~k].max()
+            assert lo_kept >= hi_drop
+            if lo_kept == hi_drop:  # a tie at the cut goes to the lower term id
+                assert ids[k & (v == lo_kept)].max() < ids[nz & ~k & (v == hi_drop)].min()
+
+
+def test_vnp_keeps_the_largest_entries_with_id_ties():
+    rng = np.random.default_rng(41)
+    csr = synth.random_csr(rng, 300, 80, 40, signed=True)
+    csr.values[::7] = np.round(csr.values[::7])  # many exact ties in |x|
+    for vn in (1, 3, 10, 100):
+        _vnp_invariants(csr, vn, oracle.vnp_prune(csr, vn))
+
+
+def test_vnp_with_mrp_counts_is_mrp():
+    """MRP keeps a prefix of the same order pi, so VNP with each row's MRP count agrees."""
+    rng = np.random.default_rng(42)
+    csr = synth.random_csr(rng, 200, 500, 60)
+    keep = oracle.mass_prune(csr, 0.6)
+    for r in range(csr.n_rows):
+        a, b = csr.indptr[r], csr.indptr[r + 1]
+        row = synth.Csr(np.array([0, b - a]), csr.indices[a:b], csr.values[a:b], csr.n_cols)
+        assert (oracle.vnp_prune(row, int(keep[a:b].sum())) == keep[a:b]).all()
+
+
+def test_lp_is_vnp_of_the_transpose():
+    """List pruning keeps, per term, what VNP keeps per row of the transposed matrix
+    (there the ties in |x| go to the lower document id)."""
+    rng = np.random.default_rng(43)
+    csr = synth.random_csr(rng, 400, 60, 30, signed=True)
+    csr.values[::5] = np.round(csr.values[::5] * 2) / 2
+    t, order = _transpose(csr)
+    for lmax in (1, 4, 25, 10_000):
+        keep = oracle.lp_prune(csr, lmax)
+        kt = oracle.vnp_prune(t, lmax)
+        assert (keep[order] == kt).all()
+        counts = np.bincount(csr.indices[keep.astype(bool)], minlength=csr.n_cols)
+        assert (counts == np.minimum(np.bincount(csr.indices[csr.values != 0], minlength=csr.n_cols), lmax)).all()
+
+
+def test_lp_after_mrp_competes_only_among_mrp_entries():
+    rng = np.random.default_rng(44)
+    csr = synth.random_csr(rng, 300, 50, 25)
+    mrp = oracle.mass_prune(csr, 0.5)
+    both = oracle.lp_prune(csr, 6, keep_in=mrp)
+    assert not (both & ~mrp).any()
+    sub = oracle.apply_mask(csr, mrp)
+    assert (oracle.lp_prune(sub, 6) == both[mrp.astype(bool)]).all()
+    assert (oracle.lp_prune(csr, 10_000, keep_in=mrp) == mrp).all()
