@@ -373,8 +373,9 @@ def serving_leg(sindi, idx, args):
             "max_batch": 512, "rates": out}
 
 
-def ablation(args, n_docs=1_000_000, n_queries=1_000, gamma=100, k=10, steps=3):
-    """The pruning rules of Sec. 4.1 at several strengths on the same corpus and queries."""
+def ablation(args, n_docs=1_000_000, n_queries=1_000, gammas=(10, 30, 100), k=10, steps=3):
+    """The pruning rules of Sec. 4.1 at several strengths on the same corpus and queries,
+    each searched with several rerank pools (a pool of k shows the coarse ranking alone)."""
     import torch
     import oracle
     import paper_2509_08395_amd as sindi
@@ -392,21 +393,21 @@ def ablation(args, n_docs=1_000_000, n_queries=1_000, gamma=100, k=10, steps=3):
     for prune, kw in grid:
         idx = sindi.Index(corpus, window=wl.window, value_dtype="f16", prune=prune, **kw)
         info = idx.info()
-        ids, _ = idx.search(dq, k, gamma=gamma)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+        row = {"prune": prune, **kw, "kept_fraction": round(info["n_postings"] / corpus.nnz, 4)}
+        for gamma in gammas:
             ids, _ = idx.search(dq, k, gamma=gamma)
-        torch.cuda.synchronize()
-        qps = n_queries * steps / (time.perf_counter() - t0)
-        rec = oracle.recall_at_k(ids.cpu().numpy()[sel], truth)
-        row = {"prune": prune, **kw, "kept_fraction": round(info["n_postings"] / corpus.nnz, 4),
-               "qps": round(qps, 1), "recall_at_10": round(rec, 4)}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ids, _ = idx.search(dq, k, gamma=gamma)
+            torch.cuda.synchronize()
+            row[f"qps_g{gamma}"] = round(n_queries * steps / (time.perf_counter() - t0), 1)
+            row[f"recall_at_10_g{gamma}"] = round(oracle.recall_at_k(ids.cpu().numpy()[sel], truth), 4)
         log(f"ablation {row}")
         rows.append(row)
         idx.close()
     return {"ablation": "pruning rules (Sec. 4.1)", "workload": wl.name, "n_docs": n_docs,
-            "n_queries": n_queries, "recall_sample": len(sel), "gamma": gamma, "k": k,
+            "n_queries": n_queries, "recall_sample": len(sel), "gammas": list(gammas), "k": k,
             "value_storage": "f16", "rows": rows}
 
 
