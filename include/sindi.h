@@ -70,6 +70,10 @@ typedef struct {
     int32_t prune;           /* sindi_prune: which entries of the corpus the lists keep  */
     int32_t vn;              /* SINDI_PRUNE_VNP: entries kept per document, >= 1         */
     int64_t list_len;        /* SINDI_PRUNE_LP, _MRP_LP: entries kept per term list, >= 1 */
+    int32_t gpu_build;       /* 0: prune and lay out the lists on the host; 1: on the current
+                                HIP device (MRP and VNP only; rows of at most 8192 entries);
+                                the index is the same bit for bit                          */
+    int32_t reserved_;
 } sindi_build_params;
 
 /*
@@ -127,8 +131,9 @@ typedef struct sindi_index sindi_index;
  * Alg. 4.  Both live in device memory owned by the returned handle.
  * Values stored as FP16/BF16 are rounded to nearest even; an FP16 overflow
  * (|x| > 65504) returns SINDI_E_RANGE.
- * corpus->on_device must be 0.  *out receives the handle (free with
- * sindi_index_free).  Synchronous: returns after the upload completes.
+ * The corpus may be device memory only with params->gpu_build = 1 (it is
+ * then validated on the device and copied).  *out receives the handle (free
+ * with sindi_index_free).  Synchronous: returns after the build completes.
  */
 sindi_status sindi_build(const sindi_csr *corpus, const sindi_build_params *params, void *stream,
                          sindi_index **out);

@@ -107,14 +107,20 @@ class Index:
     """A SINDI index in device memory (Alg. 3: pruned window lists + unpruned corpus)."""
 
     def __init__(self, corpus, alpha=1.0, window=100_000, value_dtype="f32", tile=0, stream=None,
-                 prune="mrp", vn=0, list_len=0):
+                 prune="mrp", vn=0, list_len=0, gpu_build=False):
+        """corpus: a host CSR, or a DeviceCsr (then gpu_build must be True)."""
         lib = _lib.load()
-        h = _HostCsr(corpus)
+        if isinstance(corpus, DeviceCsr):
+            h, cs = corpus, corpus.struct()
+        else:
+            h = _HostCsr(corpus)
+            cs = h.struct()
         params = _lib.SindiBuildParams(float(alpha), int(window), DTYPES[value_dtype], int(tile),
-                                       _lib.PRUNE[prune], int(vn), int(list_len))
+                                       _lib.PRUNE[prune], int(vn), int(list_len),
+                                       1 if gpu_build else 0, 0)
         handle = ctypes.c_void_p()
-        _lib.check(lib.sindi_build(ctypes.byref(h.struct()), ctypes.byref(params),
-                                   _stream(stream), ctypes.byref(handle)))
+        _lib.check(lib.sindi_build(ctypes.byref(cs), ctypes.byref(params), _stream(stream),
+                                   ctypes.byref(handle)))
         self._h = handle
         self.n_cols = h.n_cols
         self.value_dtype = value_dtype

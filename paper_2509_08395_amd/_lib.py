@@ -24,7 +24,8 @@ class SindiCsr(ctypes.Structure):
 class SindiBuildParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("window", ctypes.c_int64),
                 ("value_dtype", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("prune", ctypes.c_int32), ("vn", ctypes.c_int32), ("list_len", ctypes.c_int64)]
+                ("prune", ctypes.c_int32), ("vn", ctypes.c_int32), ("list_len", ctypes.c_int64),
+                ("gpu_build", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 PRUNE = {"mrp": 0, "vnp": 1, "lp": 2, "mrp+lp": 3}

@@ -277,11 +277,122 @@ void list_prune(const sindi_csr *c, int64_t lmax, std::vector<uint8_t> &keep)
     });
 }
 
+// The same index built on the device (sindi_build.hip): pruning, per-list
+// counts, group offsets and the ordered fill run as kernels; the host only
+// lays out the tiles, scans the per-tile totals and checks the flags.
+sindi_status build_device(const sindi_csr *c, const sindi_build_params *p, hipStream_t s,
+                          sindi_index *ix, std::vector<int64_t> &tile_doc)
+{
+    const int64_t nd = c->n_rows, nc = c->n_cols, nnz = c->nnz, n_tiles = ix->n_tiles;
+    const hipMemcpyKind kind = c->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    auto oom = [](hipError_t e, const char *what) -> sindi_status {
+        if (e == hipErrorOutOfMemory) return fail(SINDI_E_OOM, "sindi_build: device allocation of %s failed", what);
+        return fail(SINDI_E_HIP, "sindi_build: %s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e;
+#define BUILD_ALLOC(buf, bytes, what)                                                          \
+    if ((e = (buf).ensure(bytes)) != hipSuccess) return oom(e, what)
+    BUILD_ALLOC(ix->indptr, (size_t)(nd + 1) * 8, "indptr");
+    BUILD_ALLOC(ix->indices, (size_t)nnz * 4 + 4, "indices");
+    BUILD_ALLOC(ix->values, (size_t)nnz * 4 + 4, "values");
+    HIP_TRY(hipMemcpyAsync(ix->indptr.p, c->indptr, (size_t)(nd + 1) * 8, kind, s));
+    if (nnz) {
+        HIP_TRY(hipMemcpyAsync(ix->indices.p, c->indices, (size_t)nnz * 4, kind, s));
+        HIP_TRY(hipMemcpyAsync(ix->values.p, c->values, (size_t)nnz * 4, kind, s));
+    }
+    const int64_t *ptr = ix->indptr.as<int64_t>();
+    const int32_t *idx = ix->indices.as<int32_t>();
+    const float *val = ix->values.as<float>();
+    DBuf err, keep, long_rows, n_long, cnt, kept, tgroups;
+    BUILD_ALLOC(err, 4, "flags");
+    HIP_TRY(launch_fill_u32(err.as<uint32_t>(), 1, 0u, s));
+    auto flags = [&](int32_t &out_err) -> sindi_status {
+        HIP_TRY(hipMemcpyAsync(&out_err, err.p, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SINDI_OK;
+    };
+    int32_t ferr = 0;
+    sindi_status st;
+    if (c->on_device) {
+        HIP_TRY(build_check_rows(ptr, idx, val, nd, nc, nnz, err.as<int32_t>(), s));
+        if ((st = flags(ferr)) != SINDI_OK) return st;
+        if (ferr)
+            return fail(SINDI_E_INVALID,
+                        "sindi_build: malformed corpus rows (flags 0x%x: 1 row pointers, 2 term "
+                        "id range, 4 order, 8 non-finite)", ferr);
+    }
+    // Alg. 3 line 3 on the device
+    BUILD_ALLOC(keep, (size_t)nnz + 4, "keep mask");
+    BUILD_ALLOC(long_rows, (size_t)nd * 4 + 4, "long-row list");
+    BUILD_ALLOC(n_long, 4, "counter");
+    HIP_TRY(launch_fill_u32(n_long.as<uint32_t>(), 1, 0u, s));
+    const int32_t mode = p->prune == SINDI_PRUNE_VNP ? SINDI_PRUNE_VNP : SINDI_PRUNE_MRP;
+    HIP_TRY(build_prune_rows(ptr, idx, val, nd, mode, p->alpha, p->vn, keep.as<uint8_t>(),
+                             long_rows.as<int32_t>(), n_long.as<uint32_t>(), err.as<int32_t>(), s));
+    uint32_t h_long = 0;
+    HIP_TRY(hipMemcpyAsync(&h_long, n_long.p, 4, hipMemcpyDeviceToHost, s));
+    if ((st = flags(ferr)) != SINDI_OK) return st;
+    if (ferr & 128)
+        return fail(SINDI_E_INVALID, "sindi_build: a row holds more than %d entries; build it on "
+                    "the host (gpu_build = 0)", kLongRow);
+    HIP_TRY(build_prune_long(ptr, idx, val, long_rows.as<int32_t>(), (int32_t)h_long, mode,
+                             p->alpha, p->vn, keep.as<uint8_t>(), s));
+    long_rows.release();
+    // Alg. 1: list sizes per (tile, term)
+    const size_t stride = (size_t)nc + 1;
+    BUILD_ALLOC(ix->tile_doc, tile_doc.size() * 8, "tile_doc");
+    HIP_TRY(hipMemcpyAsync(ix->tile_doc.p, tile_doc.data(), tile_doc.size() * 8, hipMemcpyHostToDevice, s));
+    BUILD_ALLOC(cnt, (size_t)n_tiles * stride * 4, "list counts");
+    BUILD_ALLOC(ix->term_max, (size_t)nc * 4, "term maxima");
+    BUILD_ALLOC(kept, 8, "counter");
+    HIP_TRY(launch_fill_u32(cnt.as<uint32_t>(), (int64_t)n_tiles * (int64_t)stride, 0u, s));
+    HIP_TRY(launch_fill_u32(ix->term_max.as<uint32_t>(), nc, 0u, s));
+    HIP_TRY(launch_fill_u32(kept.as<uint32_t>(), 2, 0u, s));
+    HIP_TRY(build_count_lists(ptr, idx, val, keep.as<uint8_t>(), nd, nc, ix->tile_doc.as<int64_t>(),
+                              n_tiles, p->value_dtype, cnt.as<uint32_t>(),
+                              ix->term_max.as<uint32_t>(), kept.as<unsigned long long>(),
+                              err.as<int32_t>(), s));
+    BUILD_ALLOC(ix->term_goff, (size_t)n_tiles * stride * 4, "term offsets");
+    BUILD_ALLOC(tgroups, (size_t)n_tiles * 8 + 8, "tile totals");
+    HIP_TRY(build_list_offsets(cnt.as<uint32_t>(), n_tiles, nc, ix->term_goff.as<uint32_t>(),
+                               tgroups.as<int64_t>(), err.as<int32_t>(), s));
+    std::vector<int64_t> tile_post((size_t)n_tiles + 1, 0);
+    unsigned long long h_kept = 0;
+    HIP_TRY(hipMemcpyAsync(tile_post.data() + 1, tgroups.p, (size_t)n_tiles * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h_kept, kept.p, 8, hipMemcpyDeviceToHost, s));
+    if ((st = flags(ferr)) != SINDI_OK) return st;
+    if (ferr & 32) return fail(SINDI_E_RANGE, "sindi_build: a kept value overflows the storage type");
+    if (ferr & 16) return fail(SINDI_E_INVALID, "sindi_build: a tile holds 2^32 or more postings");
+    for (int64_t t = 0; t < n_tiles; ++t) tile_post[t + 1] = tile_post[t] + 4 * tile_post[t + 1];
+    const int64_t n_slots = tile_post[n_tiles];
+    if (n_slots >= ((int64_t)1 << 34))
+        return fail(SINDI_E_INVALID, "sindi_build: more than 2^34 index postings");
+    ix->n_post = (int64_t)h_kept;
+    ix->n_slots = n_slots;
+    BUILD_ALLOC(ix->tile_post, tile_post.size() * 8, "tile_post");
+    HIP_TRY(hipMemcpyAsync(ix->tile_post.p, tile_post.data(), tile_post.size() * 8, hipMemcpyHostToDevice, s));
+    const size_t vbytes = p->value_dtype == SINDI_F32 ? 4 : 2;
+    BUILD_ALLOC(ix->post_doc, ((size_t)n_slots + 4) * 2, "posting ids");
+    BUILD_ALLOC(ix->post_val, ((size_t)n_slots + 4) * vbytes, "posting values");
+    HIP_TRY(launch_fill_u32(ix->post_val.as<uint32_t>(), (int64_t)(ix->post_val.bytes / 4), 0u, s));
+    HIP_TRY(launch_fill_u32(ix->post_doc.as<uint32_t>(), (int64_t)(ix->post_doc.bytes / 4), 0u, s));
+    HIP_TRY(build_fill_lists(ptr, idx, val, keep.as<uint8_t>(), ix->tile_doc.as<int64_t>(),
+                             ix->tile_post.as<int64_t>(), ix->term_goff.as<uint32_t>(), n_tiles, nc,
+                             p->value_dtype, ix->post_doc.as<uint16_t>(), ix->post_val.p, s));
+    HIP_TRY(build_fill_pads(ix->term_goff.as<uint32_t>(), cnt.as<uint32_t>(), ix->tile_post.as<int64_t>(),
+                            n_tiles, nc, ix->post_doc.as<uint16_t>(), s));
+    HIP_TRY(hipStreamSynchronize(s));
+#undef BUILD_ALLOC
+    ix->h_tile_doc = std::move(tile_doc);
+    return SINDI_OK;
+}
+
 sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStream_t s,
                         sindi_index **out)
 {
     if (!c || !p || !out) return fail(SINDI_E_INVALID, "sindi_build: null argument");
-    if (c->on_device) return fail(SINDI_E_INVALID, "sindi_build: corpus must be host memory");
+    if (c->on_device && !p->gpu_build)
+        return fail(SINDI_E_INVALID, "sindi_build: a device corpus needs gpu_build = 1");
     if (p->prune < SINDI_PRUNE_MRP || p->prune > SINDI_PRUNE_MRP_LP)
         return fail(SINDI_E_INVALID, "sindi_build: unknown pruning rule %d", p->prune);
     const bool use_mrp = p->prune == SINDI_PRUNE_MRP || p->prune == SINDI_PRUNE_MRP_LP;
@@ -291,6 +402,10 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     if (p->prune == SINDI_PRUNE_VNP && p->vn < 1)
         return fail(SINDI_E_INVALID, "sindi_build: vn must be >= 1");
     if (use_lp && p->list_len < 1) return fail(SINDI_E_INVALID, "sindi_build: list_len must be >= 1");
+    if (p->gpu_build && use_lp)
+        return fail(SINDI_E_INVALID, "sindi_build: list pruning is built on the host (gpu_build = 0)");
+    if (p->gpu_build && c->n_rows >= (int64_t)INT32_MAX)
+        return fail(SINDI_E_INVALID, "sindi_build: the device build takes fewer than 2^31 documents");
     if (p->window < 1) return fail(SINDI_E_INVALID, "sindi_build: window must be >= 1");
     if (p->value_dtype < 0 || p->value_dtype > 2)
         return fail(SINDI_E_INVALID, "sindi_build: unknown value dtype %d", p->value_dtype);
@@ -299,7 +414,10 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
         return fail(SINDI_E_INVALID, "sindi_build: tile must be in [1, %d]", kTileMax);
     if (c->n_rows >= (int64_t)0xFFFFFFFF)
         return fail(SINDI_E_INVALID, "sindi_build: too many documents");
-    sindi_status st = validate_host_csr(c, "corpus", 0);
+    if (c->n_rows < 0 || c->n_cols < 1 || c->n_cols > INT32_MAX || c->nnz < 0 || !c->indptr ||
+        (c->nnz > 0 && (!c->indices || !c->values)))
+        return fail(SINDI_E_INVALID, "sindi_build: bad corpus shape or null array");
+    sindi_status st = c->on_device ? SINDI_OK : validate_host_csr(c, "corpus", 0);
     if (st != SINDI_OK) return st;
 
     sindi_index *ix = new (std::nothrow) sindi_index();
@@ -343,6 +461,12 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     if ((int64_t)accumulate_lds_bytes(1, ix->tile_stride) > ix->max_lds)
         return fail(SINDI_E_INVALID, "sindi_build: tile of %d documents exceeds on-chip memory",
                     tmax);
+
+    if (p->gpu_build) {
+        if ((st = build_device(c, p, s, ix, tile_doc)) != SINDI_OK) return st;
+        *out = guard.release();
+        return SINDI_OK;
+    }
 
     // Alg. 3 line 3: alpha-mass subvector of every document (or the rule chosen)
     std::vector<uint8_t> keep((size_t)c->nnz);

@@ -60,6 +60,8 @@ constexpr int kEntryBlock = 512;       // (query, term) entries merged per pass 
 constexpr int kChunk = 64;             // 4-posting groups per list chunk (one per lane)
 constexpr uint32_t kGoffMask = 0x3FFFFFFFu;
 constexpr int kTileMax = 16384;        // documents per tile (4 * local id fits 16 bits)
+constexpr int kLongRow = 8192;         // longest corpus row of the device build
+constexpr int kFillTerms = 32768;      // list cursors per pass of the device build's fill
 
 // LDS of one accumulate workgroup: the score rows A[batch][tile_stride], the
 // batch's merged term list (ids + one weight per query) and a region that
@@ -106,6 +108,32 @@ hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_
                            const float *theta, int64_t cap, int32_t need, int32_t k, bool rerank,
                            int32_t max_qnnz, int64_t *out_ids, float *out_scores, int32_t *status,
                            hipStream_t s);
+
+// Device index build (sindi_build.hip); err bits: 1 row pointers, 2 term id
+// range, 4 ids not ascending, 8 non-finite, 16 a tile of 2^30 groups or more,
+// 32 a kept value overflows the storage type, 128 a row longer than kLongRow.
+hipError_t build_check_rows(const int64_t *ptr, const int32_t *idx, const float *val,
+                            int64_t n_rows, int64_t n_cols, int64_t nnz, int32_t *err,
+                            hipStream_t s);
+hipError_t build_prune_rows(const int64_t *ptr, const int32_t *idx, const float *val,
+                            int64_t n_rows, int32_t mode, double alpha, int32_t vn, uint8_t *keep,
+                            int32_t *long_rows, uint32_t *n_long, int32_t *err, hipStream_t s);
+hipError_t build_prune_long(const int64_t *ptr, const int32_t *idx, const float *val,
+                            const int32_t *rows, int32_t n_rows, int32_t mode, double alpha,
+                            int32_t vn, uint8_t *keep, hipStream_t s);
+hipError_t build_count_lists(const int64_t *ptr, const int32_t *idx, const float *val,
+                             const uint8_t *keep, int64_t n_rows, int64_t n_cols,
+                             const int64_t *tile_doc, int64_t n_tiles, int32_t dtype,
+                             uint32_t *cnt, uint32_t *term_max_bits, unsigned long long *n_kept,
+                             int32_t *err, hipStream_t s);
+hipError_t build_list_offsets(const uint32_t *cnt, int64_t n_tiles, int64_t n_cols,
+                              uint32_t *goff, int64_t *tile_groups, int32_t *err, hipStream_t s);
+hipError_t build_fill_lists(const int64_t *ptr, const int32_t *idx, const float *val,
+                            const uint8_t *keep, const int64_t *tile_doc, const int64_t *tile_post,
+                            const uint32_t *goff, int64_t n_tiles, int64_t n_cols, int32_t dtype,
+                            uint16_t *post_doc, void *post_val, hipStream_t s);
+hipError_t build_fill_pads(const uint32_t *goff, const uint32_t *cnt, const int64_t *tile_post,
+                           int64_t n_tiles, int64_t n_cols, uint16_t *post_doc, hipStream_t s);
 
 hipError_t launch_score_forward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
                                 int32_t n_cand, float *out, hipStream_t s);

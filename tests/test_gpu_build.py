@@ -1,0 +1,101 @@
+"""The index built on the device equals the host build bit for bit (Alg. 3 pruning, then
+Alg. 1's lists in the tiled 4-slot-aligned layout), for every storage type and the pruning
+rules it supports, and rejects what the host rejects."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sindi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_08395_amd as s
+    s._lib.load()
+    return s
+
+
+def _same_index(a, b):
+    ra, rb = a.export(raw=True), b.export(raw=True)
+    for key in ("tile_doc", "tile_post", "term_goff", "post_doc"):
+        assert np.array_equal(ra[key], rb[key]), key
+    va, vb = ra["post_val"], rb["post_val"]
+    assert np.array_equal(va.view(np.uint8), vb.view(np.uint8)), "post_val"
+    ia, ib = a.info(), b.info()
+    for key in ("n_postings", "n_slots", "n_tiles", "tile_max", "n_windows"):
+        assert ia[key] == ib[key], key
+
+
+def _same_search(a, b, queries, k=20, gamma=200):
+    ia, sa = a.search(queries, k, gamma=gamma)
+    ib, sb = b.search(queries, k, gamma=gamma)
+    assert torch.equal(ia, ib)
+    assert torch.equal(sa.view(torch.int32), sb.view(torch.int32))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("prune,kw", [("mrp", dict(alpha=0.5)), ("mrp", dict(alpha=1.0)),
+                                      ("vnp", dict(vn=17))])
+def test_device_build_equals_host_build(sindi, dtype, prune, kw):
+    corpus = synth.generate(30_011, 2_000, nnz=("poisson", 40.0), seed=11)
+    queries = synth.generate(32, 2_000, nnz=("poisson", 12.0), seed=11, stream=1)
+    h = sindi.Index(corpus, window=7_000, value_dtype=dtype, tile=2_048, prune=prune, **kw)
+    g = sindi.Index(corpus, window=7_000, value_dtype=dtype, tile=2_048, prune=prune, gpu_build=True, **kw)
+    _same_index(h, g)
+    _same_search(h, g, queries)
+
+
+def test_device_build_long_rows_signed_zeros_and_empty_rows(sindi):
+    """Rows up to 3,000 entries (the one-workgroup path), negative values, explicit zeros
+    (not entries) and empty rows."""
+    rng = np.random.default_rng(5)
+    corpus = synth.random_csr(rng, 4_000, 6_000, 60, signed=True)
+    long_ = synth.random_csr(rng, 40, 6_000, 3_000, signed=True, min_nnz=600)
+    indptr = np.concatenate([corpus.indptr, corpus.indptr[-1] + long_.indptr[1:]])
+    c = synth.Csr(indptr, np.concatenate([corpus.indices, long_.indices]),
+                  np.concatenate([corpus.values, long_.values]), 6_000)
+    c.values[::11] = 0.0
+    lens = np.diff(c.indptr)
+    assert (lens > 512).sum() >= 30 and (lens == 0).any()
+    queries = synth.random_csr(rng, 24, 6_000, 40, signed=True, min_nnz=1)
+    for prune, kw in (("mrp", dict(alpha=0.6)), ("vnp", dict(vn=300))):
+        h = sindi.Index(c, window=1_500, tile=700, prune=prune, **kw)
+        g = sindi.Index(c, window=1_500, tile=700, prune=prune, gpu_build=True, **kw)
+        _same_index(h, g)
+        _same_search(h, g, queries)
+
+
+def test_device_build_from_device_corpus(sindi):
+    corpus = synth.generate(12_000, 3_000, nnz=("poisson", 50.0), seed=3)
+    queries = synth.generate(16, 3_000, nnz=("poisson", 10.0), seed=3, stream=1)
+    h = sindi.Index(corpus, alpha=0.5, window=5_000, value_dtype="f16", tile=1_024)
+    g = sindi.Index(sindi.DeviceCsr.from_host(corpus), alpha=0.5, window=5_000, value_dtype="f16",
+                    tile=1_024, gpu_build=True)
+    _same_index(h, g)
+    _same_search(h, g, queries)
+
+
+def test_device_build_rejections(sindi):
+    E = sindi.SindiError
+    bad = synth.Csr(np.array([0, 2, 3]), np.array([5, 1, 7], np.int32),
+                    np.array([1.0, 2.0, 3.0], np.float32), 10)
+    with pytest.raises(E, match="order|ascending"):
+        sindi.Index(sindi.DeviceCsr.from_host(bad), alpha=0.5, window=10, gpu_build=True)
+    big = synth.Csr(np.array([0, 9_000]), np.arange(9_000, dtype=np.int32),
+                    np.ones(9_000, np.float32), 9_000)
+    with pytest.raises(E, match="more than 8192"):
+        sindi.Index(big, alpha=0.5, window=10, gpu_build=True)
+    over = synth.Csr(np.array([0, 2]), np.array([0, 1], np.int32),
+                     np.array([7e4, 1.0], np.float32), 4)
+    with pytest.raises(E, match="overflows") as ei:
+        sindi.Index(over, alpha=1.0, window=10, value_dtype="f16", gpu_build=True)
+    assert ei.value.code == sindi._lib.SINDI_E_RANGE
+    with pytest.raises(E, match="list pruning"):
+        sindi.Index(bad, window=10, prune="lp", list_len=3, gpu_build=True)
+    with pytest.raises(E, match="gpu_build"):
+        sindi.Index(sindi.DeviceCsr.from_host(over), alpha=1.0, window=10)

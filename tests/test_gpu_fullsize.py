@@ -73,3 +73,23 @@ def test_splade_8_8m_sampled_queries(sindi, dtype, coarse_rtol):
                     pool_margin=pool_margin_fn(pid, psc, cp, qs, coarse_rtol))
     truth, _ = oracle.exact_topk(corpus, qs.take_rows(np.arange(0, 24, 3)), wl.k)
     assert oracle.recall_at_k(gi[::3], truth) >= 0.99
+
+
+def test_splade_8_8m_device_build_equals_host_build(sindi):
+    import time
+    wl = WORKLOADS["splade-8.8m"]
+    corpus = wl.corpus()
+    t = time.time()
+    h = sindi.Index(corpus, alpha=wl.alpha, window=wl.window, value_dtype=wl.value_dtype)
+    th = time.time() - t
+    rh = h.export(raw=True)
+    del h
+    t = time.time()
+    g = sindi.Index(corpus, alpha=wl.alpha, window=wl.window, value_dtype=wl.value_dtype,
+                    gpu_build=True)
+    tg = time.time() - t
+    rg = g.export(raw=True)
+    print(f"host build {th:.2f} s, device build {tg:.2f} s (upload included in both)")
+    for key in ("tile_doc", "tile_post", "term_goff", "post_doc"):
+        assert np.array_equal(rh[key], rg[key]), key
+    assert np.array_equal(rh["post_val"], rg["post_val"])
