@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_count_lists(const int64_t *ptr, const i
 // One workgroup per tile: group offsets of its lists (exclusive scan of
 // ceil(count / 4) over terms), pad counts in the top two bits, the tile's
 // group total in goff[n_cols] and tile_groups[t]; err bit 16 if the tile holds
-// 2^30 groups or more.
+// more than kTileGroupsMax groups.
 __global__ __launch_bounds__(256) void k_list_offsets(const uint32_t *cnt, int64_t n_cols,
                                                       uint32_t *goff, int64_t *tile_groups,
                                                       int32_t *err)
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void k_list_offsets(const uint32_t *cnt, int64
     if (threadIdx.x == 0) {
         g[n_cols] = (uint32_t)(s_base & kGoffMask);
         tile_groups[t] = (int64_t)s_base;
-        if (s_base > kGoffMask) atomicOr(err, 16);
+        if (s_base > kTileGroupsMax) atomicOr(err, 16);
     }
 }
 

@@ -130,7 +130,11 @@ uint16_t to_bf16(float x)
     return (uint16_t)(u >> 16);
 }
 
-constexpr int32_t kDefaultTile = 8192;
+// Largest tile of a window split: three 512-thread scoring workgroups (one
+// query each) still share a CU's 160 KB of LDS, and fewer, larger tiles cut the
+// per-tile work (list scan, barriers) per posting.
+constexpr int32_t kDefaultTile = 10240;
+static_assert(3 * accumulate_lds_bytes(1, kDefaultTile) <= 160 * 1024, "default tile too large");
 constexpr int32_t kDefaultBatch = 1;
 constexpr int32_t kDefaultCandCap = 32768;
 constexpr int32_t kDefaultSampleTiles = 32;
@@ -362,7 +366,9 @@ sindi_status build_device(const sindi_csr *c, const sindi_build_params *p, hipSt
     HIP_TRY(hipMemcpyAsync(&h_kept, kept.p, 8, hipMemcpyDeviceToHost, s));
     if ((st = flags(ferr)) != SINDI_OK) return st;
     if (ferr & 32) return fail(SINDI_E_RANGE, "sindi_build: a kept value overflows the storage type");
-    if (ferr & 16) return fail(SINDI_E_INVALID, "sindi_build: a tile holds 2^32 or more postings");
+    if (ferr & 16)
+        return fail(SINDI_E_INVALID, "sindi_build: a tile needs more than %u groups of 4 postings",
+                    kTileGroupsMax);
     for (int64_t t = 0; t < n_tiles; ++t) tile_post[t + 1] = tile_post[t] + 4 * tile_post[t + 1];
     const int64_t n_slots = tile_post[n_tiles];
     if (n_slots >= ((int64_t)1 << 34))
@@ -372,8 +378,8 @@ sindi_status build_device(const sindi_csr *c, const sindi_build_params *p, hipSt
     BUILD_ALLOC(ix->tile_post, tile_post.size() * 8, "tile_post");
     HIP_TRY(hipMemcpyAsync(ix->tile_post.p, tile_post.data(), tile_post.size() * 8, hipMemcpyHostToDevice, s));
     const size_t vbytes = p->value_dtype == SINDI_F32 ? 4 : 2;
-    BUILD_ALLOC(ix->post_doc, ((size_t)n_slots + 4) * 2, "posting ids");
-    BUILD_ALLOC(ix->post_val, ((size_t)n_slots + 4) * vbytes, "posting values");
+    BUILD_ALLOC(ix->post_doc, ((size_t)n_slots + kTailSlots) * 2, "posting ids");
+    BUILD_ALLOC(ix->post_val, ((size_t)n_slots + kTailSlots) * vbytes, "posting values");
     HIP_TRY(launch_fill_u32(ix->post_val.as<uint32_t>(), (int64_t)(ix->post_val.bytes / 4), 0u, s));
     HIP_TRY(launch_fill_u32(ix->post_doc.as<uint32_t>(), (int64_t)(ix->post_doc.bytes / 4), 0u, s));
     HIP_TRY(build_fill_lists(ptr, idx, val, keep.as<uint8_t>(), ix->tile_doc.as<int64_t>(),
@@ -519,7 +525,7 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
                     cnt[j] = (uint32_t)g | (pad << 30);
                     g += (n + 3u) / 4u;
                 }
-                if (g > kGoffMask) tile_big = 1;
+                if (g > kTileGroupsMax) tile_big = 1;
                 cnt[nc] = (uint32_t)(g & kGoffMask);
                 tile_post[t + 1] = (int64_t)g * 4;
             }
@@ -528,7 +534,9 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
         });
     }
     if (range_bad) return fail(SINDI_E_RANGE, "sindi_build: a kept value overflows the storage type");
-    if (tile_big) return fail(SINDI_E_INVALID, "sindi_build: a tile holds 2^32 or more postings");
+    if (tile_big)
+        return fail(SINDI_E_INVALID, "sindi_build: a tile needs more than %u groups of 4 postings",
+                    kTileGroupsMax);
     for (int64_t t = 0; t < n_tiles; ++t) tile_post[t + 1] += tile_post[t];
     const int64_t n_slots = tile_post[n_tiles];
     if (n_slots >= ((int64_t)1 << 34))
@@ -536,8 +544,8 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     ix->n_post = n_post;
     ix->n_slots = n_slots;
     const size_t vbytes = p->value_dtype == SINDI_F32 ? 4 : 2;
-    std::vector<uint16_t> post_doc((size_t)n_slots + 4, 0);
-    std::vector<uint8_t> post_val(((size_t)n_slots + 4) * vbytes, 0);
+    std::vector<uint16_t> post_doc((size_t)n_slots + kTailSlots, 0);
+    std::vector<uint8_t> post_val(((size_t)n_slots + kTailSlots) * vbytes, 0);
     parallel_for(n_tiles, [&](int64_t lo, int64_t hi) {
         std::vector<uint64_t> fill(stride);
         for (int64_t t = lo; t < hi; ++t) {

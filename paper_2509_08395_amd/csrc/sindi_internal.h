@@ -21,9 +21,11 @@ struct DevIndex {
                                    // group (term_goff & kGoffMask) of the tile and ends, pads
                                    // included, where the next term's list starts; top 2 bits:
                                    // pad entries at its end
-    const uint16_t *post_doc;      // [n_slots] 4 * (document id - tile_doc[t]): the byte offset of
-                                   // the document's score word in a row; pads repeat the last one
-    const void *post_val;          // [n_slots] value (f32 / f16 / bf16 bits); pads hold 0
+    const uint16_t *post_doc;      // [n_slots + kTailSlots] 4 * (document id - tile_doc[t]): the
+                                   // byte offset of the document's score word in a row; pads
+                                   // repeat the last one
+    const void *post_val;          // [n_slots + kTailSlots] value (f32 / f16 / bf16 bits); pads
+                                   // and the tail hold 0
     const float *term_max;         // [n_cols] largest |stored value| in the term's lists
     const int64_t *indptr;         // unpruned corpus CSR, [n_docs + 1]
     const int32_t *indices;        // [nnz]
@@ -59,6 +61,12 @@ constexpr int kQueryHash = 8192;       // rerank hash slots (query nnz <= kQuery
 constexpr int kEntryBlock = 512;       // (query, term) entries merged per pass in the accumulate kernel
 constexpr int kChunk = 64;             // 4-posting groups per list chunk (one per lane)
 constexpr uint32_t kGoffMask = 0x3FFFFFFFu;
+// Most 4-posting groups in one tile: a chunk addresses its groups by 32-bit
+// byte offsets from the tile's first group (16 B per group for FP32 values),
+// and may read up to kChunk - 1 groups past a list's end.
+constexpr uint32_t kTileGroupsMax = (1u << 28) - kChunk;
+// Zero postings after the last slot, so those reads stay inside the arrays.
+constexpr int kTailSlots = 4 * kChunk;
 constexpr int kTileMax = 16384;        // documents per tile (4 * local id fits 16 bits)
 constexpr int kLongRow = 8192;         // longest corpus row of the device build
 constexpr int kFillTerms = 32768;      // list cursors per pass of the device build's fill
@@ -67,7 +75,7 @@ constexpr int kFillTerms = 32768;      // list cursors per pass of the device bu
 // batch's merged term list (ids + one weight per query) and a region that
 // first holds the merge sort keys, then the tile's non-empty lists (group
 // start, group count, first chunk, weights).
-inline size_t accumulate_lds_bytes(int batch, int tile_stride)
+constexpr size_t accumulate_lds_bytes(int batch, int tile_stride)
 {
     const size_t merge = (size_t)kEntryBlock * 12;
     const size_t lists = ((size_t)3 * kEntryBlock + 4) * 4 + (size_t)kEntryBlock * batch * 4;
@@ -110,7 +118,7 @@ hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_
                            hipStream_t s);
 
 // Device index build (sindi_build.hip); err bits: 1 row pointers, 2 term id
-// range, 4 ids not ascending, 8 non-finite, 16 a tile of 2^30 groups or more,
+// range, 4 ids not ascending, 8 non-finite, 16 a tile of more than kTileGroupsMax groups,
 // 32 a kept value overflows the storage type, 128 a row longer than kLongRow.
 hipError_t build_check_rows(const int64_t *ptr, const int32_t *idx, const float *val,
                             int64_t n_rows, int64_t n_cols, int64_t nnz, int32_t *err,

@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "sindi_internal.h"
 
@@ -55,6 +56,27 @@ __device__ __forceinline__ int4 fresh_zero4()
 
 // Wave-uniform copy of a value (scalar register).
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// A wave-uniform pointer to global memory, held in scalar registers, and
+// loads of 8 or 16 bytes at a 32-bit byte offset from it (the scalar base +
+// vector offset form of the global load).
+using gbytes = const unsigned char __attribute__((address_space(1))) *;
+__device__ __forceinline__ gbytes uni_ptr(const void *p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    return (gbytes)(((uint64_t)uni((uint32_t)(a >> 32)) << 32) | uni((uint32_t)a));
+}
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void load_at(gbytes p, uint32_t off, uint2 &r)
+{
+    const u32x2 v = *(const u32x2 __attribute__((address_space(1))) *)(p + off);
+    r = make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ void load_at(gbytes p, uint32_t off, uint4 &r)
+{
+    const u32x4 v = *(const u32x4 __attribute__((address_space(1))) *)(p + off);
+    r = make_uint4(v.x, v.y, v.z, v.w);
+}
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
@@ -468,9 +490,9 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (size_t)EB * B);
     uint64_t *keys = reinterpret_cast<uint64_t *>(region);                 // merge phase
     uint32_t *flag = reinterpret_cast<uint32_t *>(keys + EB);              // merge phase
-    uint32_t *l_gs = reinterpret_cast<uint32_t *>(region);                 // tile phase
-    uint32_t *l_ng = l_gs + EB;
-    uint32_t *l_cp = l_ng + EB;                                            // EB + 1 (+3)
+    uint32_t *l_base = reinterpret_cast<uint32_t *>(region);               // tile phase
+    uint32_t *l_end = l_base + EB;
+    uint32_t *l_cp = l_end + EB;                                           // EB + 1 (+3)
     float *l_w = reinterpret_cast<float *>(l_cp + EB + 4);                 // [EB][B]
     __shared__ int64_t s_qa[B];
     __shared__ int32_t s_qpre[B + 1];
@@ -627,9 +649,11 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
             const uint32_t ex = block_excl_scan<NT>(nch | (nch ? (1u << 20) : 0u), s_wsum, total);
             // the scan's barriers order these writes after the merge-phase reads
             if (nch) {
+                // chunk ci of list li covers groups [l_base + 64 ci, min(+64, l_end)) of
+                // the tile (l_base wraps below zero as an unsigned number)
                 const uint32_t li = ex >> 20;
-                l_gs[li] = gs;
-                l_ng[li] = ng;
+                l_base[li] = gs - (ex & 0xFFFFFu) * (uint32_t)kChunk;
+                l_end[li] = gs + ng;
                 l_cp[li] = ex & 0xFFFFFu;
 #pragma unroll
                 for (int b = 0; b < B; ++b) l_w[li * B + b] = u_w[tid * B + b];
@@ -671,18 +695,23 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
             const uint32_t c_beg = (uint32_t)(((uint64_t)n_chunk * (uint32_t)wave) / NW);
             const uint32_t c_end = (uint32_t)(((uint64_t)n_chunk * (uint32_t)(wave + 1)) / NW);
             if (c_beg < c_end) {
+                // the tile's groups, addressed by 32-bit byte offsets (a tile holds at
+                // most kTileGroupsMax groups; the arrays end with kTailSlots zero postings)
+                const gbytes pd_t = uni_ptr(
+                    reinterpret_cast<const unsigned char *>(ix.post_doc) + G0 * sizeof(uint2));
+                const gbytes pv_t = uni_ptr(
+                    reinterpret_cast<const unsigned char *>(ix.post_val) + G0 * sizeof(Raw));
                 uint32_t lp0 = uni(s_wl[wave]);  // list of chunk c
                 for (uint32_t c = c_beg; c < c_end;) {
                     const uint32_t lw = lp0 + (uint32_t)lane;
                     const uint32_t cpn = lw + 1 <= n_list ? l_cp[lw + 1] : 0xFFFFFFFFu;
-                    uint32_t cpl = 0, gsl = 0, ngl = 0;
+                    uint32_t basel = 0, endl = 0;
                     float wl[B];
 #pragma unroll
                     for (int b = 0; b < B; ++b) wl[b] = 0.0f;
                     if (lw < n_list) {
-                        cpl = l_cp[lw];
-                        gsl = l_gs[lw];
-                        ngl = l_ng[lw];
+                        basel = l_base[lw];
+                        endl = l_end[lw];
 #pragma unroll
                         for (int b = 0; b < B; ++b) wl[b] = l_w[lw * B + b];
                     }
@@ -693,29 +722,27 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                         Raw raw[KU];
                         uint32_t nl[KU];
                         int32_t kl[KU];
-                        // Loads are unconditional, so they leave back to back: a lane past
-                        // its chunk's end re-reads the chunk's last group, and a slot past
-                        // the window reads the tile's first group (the tile has groups, or
-                        // it would have no chunks); those lanes add nothing.
+                        // Loads are unconditional, so they leave back to back: lane l reads
+                        // group g0 + l even past its chunk's end (at most 63 groups past the
+                        // end of a list of this tile: inside the arrays), and a slot past the
+                        // window reads the tile's first groups; those lanes add nothing.
 #pragma unroll
                         for (int i = 0; i < KU; ++i) {
                             const uint32_t ci = cs + (uint32_t)i;
-                            uint64_t g0 = G0;
-                            uint32_t n = 0;
+                            uint32_t g0 = 0, n = 0;
                             int32_t k = 0;
                             if (ci < c_win) {  // wave-uniform
                                 k = (int32_t)__popcll(__ballot(cpn <= ci));
-                                const uint32_t j0 =
-                                    (ci - (uint32_t)__builtin_amdgcn_readlane((int)cpl, k)) * (uint32_t)kChunk;
+                                g0 = (uint32_t)__builtin_amdgcn_readlane((int)basel, k) +
+                                     ci * (uint32_t)kChunk;
                                 n = min((uint32_t)kChunk,
-                                        (uint32_t)__builtin_amdgcn_readlane((int)ngl, k) - j0);
-                                g0 += (uint32_t)__builtin_amdgcn_readlane((int)gsl, k) + j0;
+                                        (uint32_t)__builtin_amdgcn_readlane((int)endl, k) - g0);
                             }
                             kl[i] = k;
                             nl[i] = n;
-                            const uint32_t off = min((uint32_t)lane, n > 0 ? n - 1 : 0u);
-                            ids[i] = reinterpret_cast<const uint2 *>(ix.post_doc)[g0 + off];
-                            raw[i] = reinterpret_cast<const Raw *>(ix.post_val)[g0 + off];
+                            const uint32_t gi = g0 + (uint32_t)lane;
+                            load_at(pd_t, gi * (uint32_t)sizeof(uint2), ids[i]);
+                            load_at(pv_t, gi * (uint32_t)sizeof(Raw), raw[i]);
                         }
 #pragma unroll
                         for (int i = 0; i < KU; ++i) {
@@ -841,26 +868,34 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     // and the finalize kernel supplies them in id order; then any nonzero
                     // word needs a look.  Otherwise a word needs a look if its largest
                     // sum reaches the threshold.  Lanes past the row end read 0.
-                    const bool imp = s_imp[0];
-                    for (int base = wave * 256; base < len; base += NW * 256) {
-                        const int m0 = base + lane * 4;
-                        int4 r = make_int4(0, 0, 0, 0);
-                        if (m0 < len) {
-                            r = *reinterpret_cast<const int4 *>(A32 + m0);
-                            *reinterpret_cast<int4 *>(A32 + m0) = fresh_zero4();
+                    // The two cases are separate loops (IMP a compile-time flag).
+                    auto read_out = [&](auto imp_c) {
+                        constexpr bool IMP = decltype(imp_c)::value;
+                        for (int base = wave * 256; base < len; base += NW * 256) {
+                            const int m0 = base + lane * 4;
+                            int4 r = make_int4(0, 0, 0, 0);
+                            if (m0 < len) {
+                                r = *reinterpret_cast<const int4 *>(A32 + m0);
+                                *reinterpret_cast<int4 *>(A32 + m0) = fresh_zero4();
+                            }
+                            const bool look = IMP ? ((r.x | r.y | r.z | r.w) != 0)
+                                                  : max(max(r.x, r.y), max(r.z, r.w)) >= th;
+                            if (__ballot(look) == 0) continue;  // the common case
+                            bool ok[4];
+                            ok[0] = r.x >= th && (!IMP || r.x != 0) && m0 < len;
+                            ok[1] = r.y >= th && (!IMP || r.y != 0) && m0 + 1 < len;
+                            ok[2] = r.z >= th && (!IMP || r.z != 0) && m0 + 2 < len;
+                            ok[3] = r.w >= th && (!IMP || r.w != 0) && m0 + 3 < len;
+                            const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv,
+                                                 (float)r.z * qinv, (float)r.w * qinv};
+                            emit_candidates<4>(sv, ok, d0 + m0, count + slot,
+                                               cand + (size_t)slot * cap, cap);
                         }
-                        const bool look = imp ? ((r.x | r.y | r.z | r.w) != 0)
-                                              : max(max(r.x, r.y), max(r.z, r.w)) >= th;
-                        if (__ballot(look) == 0) continue;  // the common case
-                        bool ok[4];
-                        ok[0] = r.x >= th && (!imp || r.x != 0) && m0 < len;
-                        ok[1] = r.y >= th && (!imp || r.y != 0) && m0 + 1 < len;
-                        ok[2] = r.z >= th && (!imp || r.z != 0) && m0 + 2 < len;
-                        ok[3] = r.w >= th && (!imp || r.w != 0) && m0 + 3 < len;
-                        const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv, (float)r.z * qinv,
-                                             (float)r.w * qinv};
-                        emit_candidates<4>(sv, ok, d0 + m0, count + slot, cand + (size_t)slot * cap, cap);
-                    }
+                    };
+                    if (s_imp[0])
+                        read_out(std::true_type{});
+                    else
+                        read_out(std::false_type{});
                 }
             }
         }
@@ -1224,7 +1259,7 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
     const int64_t n_iter = SAMPLE ? n_sample : ix.n_tiles;
     // Contiguous tile ranges per workgroup (see the kernel); the range length
     // keeps the grid at least a few times the chip's resident workgroups.
-    int64_t per = tiles_per_wg > 0 ? tiles_per_wg : 32;
+    int64_t per = tiles_per_wg > 0 ? tiles_per_wg : 16;
     while (per > 1 && n_batches * ((n_iter + per - 1) / per) < 4096) per >>= 1;
     int64_t groups = (n_iter + per - 1) / per;
     if (groups > 65535) {
