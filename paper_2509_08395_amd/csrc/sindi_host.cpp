@@ -131,10 +131,13 @@ uint16_t to_bf16(float x)
 }
 
 // Largest tile of a window split: three 512-thread scoring workgroups (one
-// query each) still share a CU's 160 KB of LDS, and fewer, larger tiles cut the
-// per-tile work (list scan, barriers) per posting.
-constexpr int32_t kDefaultTile = 10240;
-static_assert(3 * accumulate_lds_bytes(1, kDefaultTile) <= 160 * 1024, "default tile too large");
+// query each, of up to 256 coarse terms) still share a CU's 160 KB of LDS, and
+// fewer, larger tiles cut the per-tile work (list scan, barriers) per posting.
+// (LDS is allocated in 512-byte units; the kernel's static LDS is under 128 bytes.)
+constexpr int32_t kDefaultTile = 12500;
+static_assert(3 * ((accumulate_lds_bytes(1, kDefaultTile, 256) + 128 + 511) / 512 * 512) <=
+                  160 * 1024,
+              "default tile too large");
 constexpr int32_t kDefaultBatch = 1;
 constexpr int32_t kDefaultCandCap = 32768;
 constexpr int32_t kDefaultSampleTiles = 32;
@@ -722,7 +725,7 @@ sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl
             HIP_TRY(timed(kProfSample, s, [&] {
                 return launch_accumulate(dix, dq, dc, pl.batch, true, ws.slot_q.as<int32_t>(), ns,
                                          pl.n_sample, ws.maxima.as<float>(), nullptr, nullptr,
-                                         nullptr, 0, pl.tile_run, s);
+                                         nullptr, 0, pl.tile_run, pl.max_qnnz, s);
             }));
             HIP_TRY(timed(kProfTheta, s, [&] {
                 return launch_theta(ws.maxima.as<float>(), pl.n_max, pl.rank, ns,
@@ -733,7 +736,7 @@ sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl
         HIP_TRY(timed(kProfScore, s, [&] {
             return launch_accumulate(dix, dq, dc, pl.batch, false, ws.slot_q.as<int32_t>(), ns, 0,
                                      nullptr, ws.theta.as<float>(), ws.count.as<uint32_t>(),
-                                     ws.cand.as<uint64_t>(), pl.cap, pl.tile_run, s);
+                                     ws.cand.as<uint64_t>(), pl.cap, pl.tile_run, pl.max_qnnz, s);
         }));
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
@@ -768,7 +771,7 @@ sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
         HIP_TRY(timed(kProfScore, s, [&] {
             return launch_accumulate(dix, dq, dc, 1, false, ws.slot_q.as<int32_t>(), ns, 0, nullptr,
                                      ws.theta.as<float>(), ws.count.as<uint32_t>(),
-                                     ws.cand.as<uint64_t>(), cap_all, pl.tile_run, s);
+                                     ws.cand.as<uint64_t>(), cap_all, pl.tile_run, pl.max_qnnz, s);
         }));
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),

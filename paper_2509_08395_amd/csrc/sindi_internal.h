@@ -71,16 +71,28 @@ constexpr int kTileMax = 16384;        // documents per tile (4 * local id fits 
 constexpr int kLongRow = 8192;         // longest corpus row of the device build
 constexpr int kFillTerms = 32768;      // list cursors per pass of the device build's fill
 
-// LDS of one accumulate workgroup: the score rows A[batch][tile_stride], the
-// batch's merged term list (ids + one weight per query) and a region that
-// first holds the merge sort keys, then the tile's non-empty lists (group
-// start, group count, first chunk, weights).
-constexpr size_t accumulate_lds_bytes(int batch, int tile_stride)
+// LDS of one accumulate workgroup: the score rows A[batch][tile_stride], for
+// batch >= 2 the merged term list (ids + one weight per query, eb entries per
+// merge pass) and a region that first holds the merge sort keys, then the
+// tile's non-empty lists (first group, end, first chunk, weights).  A single
+// query keeps its terms in registers and needs neither the list nor the keys.
+constexpr size_t accumulate_lds_bytes(int batch, int tile_stride, int eb = kEntryBlock)
 {
-    const size_t merge = (size_t)kEntryBlock * 12;
-    const size_t lists = ((size_t)3 * kEntryBlock + 4) * 4 + (size_t)kEntryBlock * batch * 4;
-    return (size_t)batch * tile_stride * 4 + (size_t)kEntryBlock * 4 +
-           (size_t)kEntryBlock * batch * 4 + (merge > lists ? merge : lists);
+    const size_t lists = ((size_t)3 * eb + 4) * 4 + (size_t)eb * batch * 4;
+    if (batch == 1) return (size_t)tile_stride * 4 + lists;
+    const size_t merge = (size_t)eb * 12;
+    return (size_t)batch * tile_stride * 4 + (size_t)eb * 4 + (size_t)eb * batch * 4 +
+           (merge > lists ? merge : lists);
+}
+
+// Entries merged per pass for a batch of `batch` queries of at most
+// `max_terms` coarse terms each: a power of two in [64, kEntryBlock] (more
+// entries take several passes), so short queries leave LDS for larger tiles.
+inline int entry_block(int batch, int64_t max_terms)
+{
+    int eb = 64;
+    while (eb < kEntryBlock && (int64_t)eb < (int64_t)batch * max_terms) eb <<= 1;
+    return eb;
 }
 
 // Status codes written per query slot by the finalize kernel.
@@ -97,7 +109,7 @@ hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevC
                              int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
                              int32_t n_sample_tiles, float *maxima, const float *theta,
                              uint32_t *count, uint64_t *cand, int64_t cap, int32_t tiles_per_wg,
-                             hipStream_t s);
+                             int32_t max_terms, hipStream_t s);
 
 hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,
                         float *theta, hipStream_t s);

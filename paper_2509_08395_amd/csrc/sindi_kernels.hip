@@ -474,20 +474,23 @@ template <int VT, int B, bool SAMPLE>
 __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_accumulate(
     DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
     int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
-    int64_t cap, int32_t tiles_per_wg)
+    int64_t cap, int32_t tiles_per_wg, int32_t eb)
 {
-    constexpr int NT = kAccThreads, NW = NT / kWave, EB = kEntryBlock;
+    constexpr int NT = kAccThreads, NW = NT / kWave;
+    const int EB = eb;  // entries merged per pass: a power of two, at most NT
     constexpr bool PACK = B >= 2;
     constexpr int NP = PACK ? B / 2 : 1;  // score words per document
     constexpr int KU = VT == 0 ? 4 : 8;   // chunks in flight per wave
-    static_assert(EB == NT, "one merged entry per thread");
+    static_assert(kEntryBlock <= NT, "at most one merged entry per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = ix.tile_stride;
     // PACK: uint64 [NP][T]; else int32 [T].  Both are B * T * 4 bytes.
     unsigned char *A = smem;
+    // B >= 2: the merged term list (u_term / u_w, EB entries); one query keeps
+    // its terms in registers instead (my_term / my_w, one per thread)
     int32_t *u_term = reinterpret_cast<int32_t *>(smem + (size_t)B * T * 4);
-    float *u_w = reinterpret_cast<float *>(u_term + EB);  // [EB][B]
-    unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (size_t)EB * B);
+    float *u_w = reinterpret_cast<float *>(u_term + (B == 1 ? 0 : EB));  // [EB][B]
+    unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (B == 1 ? 0 : (size_t)EB * B));
     uint64_t *keys = reinterpret_cast<uint64_t *>(region);                 // merge phase
     uint32_t *flag = reinterpret_cast<uint32_t *>(keys + EB);              // merge phase
     uint32_t *l_base = reinterpret_cast<uint32_t *>(region);               // tile phase
@@ -543,12 +546,14 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     const int32_t n_blocks = (n_e + EB - 1) / EB;
 
     // Merge entries [e0, e0 + EB) of the batch into u_term / u_w (s_nu terms).
+    int32_t my_term = 0;
+    float my_w = 0.0f;
     auto merge = [&](int32_t e0) {
         const int32_t ne = min(EB, n_e - e0);
         if (B == 1) {  // one query: its coarse terms are already ascending and distinct
             if (tid < ne) {
-                u_term[tid] = c.ct[s_qa[0] + e0 + tid];
-                u_w[tid] = c.cw[s_qa[0] + e0 + tid];
+                my_term = c.ct[s_qa[0] + e0 + tid];
+                my_w = c.cw[s_qa[0] + e0 + tid];
             }
             if (tid == 0) s_nu = ne;
             __syncthreads();
@@ -588,7 +593,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
         uint32_t nu;
         const uint32_t ex = block_excl_scan<NT>(fresh, s_wsum, nu);
         for (int i = tid; i < (int)nu * B; i += NT) u_w[i] = 0.0f;
-        flag[tid] = ex + fresh;  // 1-based merged index of this sorted entry's term
+        if (tid < EB) flag[tid] = ex + fresh;  // 1-based merged index of this sorted entry's term
         if (tid == 0) s_nu = (int32_t)nu;
         __syncthreads();
         if (tid < ne) {
@@ -637,7 +642,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
             // with the index of their first chunk
             uint32_t gs = 0, ng = 0;
             if (tid < nu) {
-                const int32_t term = u_term[tid];
+                const int32_t term = B == 1 ? my_term : u_term[tid];
                 const uint32_t lo = have_pre ? pre_lo : toff[term];
                 const uint32_t hi = have_pre ? pre_hi : toff[term + 1];
                 gs = lo & kGoffMask;
@@ -656,7 +661,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                 l_end[li] = gs + ng;
                 l_cp[li] = ex & 0xFFFFFu;
 #pragma unroll
-                for (int b = 0; b < B; ++b) l_w[li * B + b] = u_w[tid * B + b];
+                for (int b = 0; b < B; ++b) l_w[li * B + b] = B == 1 ? my_w : u_w[tid * B + b];
             }
             const uint32_t n_list = total >> 20, n_chunk = total & 0xFFFFFu;
             if (tid == 0) l_cp[n_list] = n_chunk;
@@ -677,7 +682,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     if (tid < nu) {
                         const int64_t t2 = SAMPLE ? (tn * ix.n_tiles / n_sample) : tn;
                         const uint32_t *toff2 = ix.term_goff + (size_t)t2 * (size_t)(ix.n_cols + 1);
-                        const int32_t term = u_term[tid];
+                        const int32_t term = B == 1 ? my_term : u_term[tid];
                         pre_lo = toff2[term];
                         pre_hi = toff2[term + 1];
                     }
@@ -1250,9 +1255,10 @@ template <int VT, int B, bool SAMPLE>
 hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                           const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
                           const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
-                          int32_t tiles_per_wg, hipStream_t s)
+                          int32_t tiles_per_wg, int32_t max_terms, hipStream_t s)
 {
-    const size_t lds = accumulate_lds_bytes(B, ix.tile_stride);
+    const int eb = entry_block(B, max_terms);
+    const size_t lds = accumulate_lds_bytes(B, ix.tile_stride, eb);
     hipError_t e = set_lds(k_accumulate<VT, B, SAMPLE>, lds);
     if (e != hipSuccess) return e;
     const int64_t n_batches = (n_slots + B - 1) / B;
@@ -1269,7 +1275,8 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
     }
     dim3 grid((unsigned)n_batches, (unsigned)groups);
     hipLaunchKernelGGL((k_accumulate<VT, B, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
-                       slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, (int32_t)per);
+                       slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, (int32_t)per,
+                       (int32_t)eb);
     return hipGetLastError();
 }
 
@@ -1277,13 +1284,13 @@ template <int VT, bool SAMPLE>
 hipError_t dispatch_b(int batch, const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                       const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
                       const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
-                      int32_t tiles_per_wg, hipStream_t s)
+                      int32_t tiles_per_wg, int32_t max_terms, hipStream_t s)
 {
     switch (batch) {
-    case 1: return run_accumulate<VT, 1, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
-    case 2: return run_accumulate<VT, 2, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
-    case 4: return run_accumulate<VT, 4, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
-    case 8: return run_accumulate<VT, 8, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, s);
+    case 1: return run_accumulate<VT, 1, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+    case 2: return run_accumulate<VT, 2, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+    case 4: return run_accumulate<VT, 4, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+    case 8: return run_accumulate<VT, 8, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1305,18 +1312,18 @@ hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevC
                              int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
                              int32_t n_sample_tiles, float *maxima, const float *theta,
                              uint32_t *count, uint64_t *cand, int64_t cap, int32_t tiles_per_wg,
-                             hipStream_t s)
+                             int32_t max_terms, hipStream_t s)
 {
     if (n_slots == 0 || ix.n_tiles == 0) return hipSuccess;
     const int vt = ix.value_dtype;
     if (sample) {
-        if (vt == 0) return dispatch_b<0, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
-        if (vt == 1) return dispatch_b<1, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
-        return dispatch_b<2, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
+        if (vt == 0) return dispatch_b<0, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+        if (vt == 1) return dispatch_b<1, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+        return dispatch_b<2, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
     }
-    if (vt == 0) return dispatch_b<0, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
-    if (vt == 1) return dispatch_b<1, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
-    return dispatch_b<2, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, s);
+    if (vt == 0) return dispatch_b<0, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+    if (vt == 1) return dispatch_b<1, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+    return dispatch_b<2, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
 }
 
 hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,
