@@ -150,12 +150,13 @@ sindi_status check_row(const sindi_server *srv, const int32_t *idx, const float 
 bool sindi_server::launch(Slot &s, std::vector<Request *> &batch)
 {
     const int32_t nb = (int32_t)batch.size();
-    int32_t kb = 1;
+    int32_t kb = 1, longest = 0;
     int64_t nnz = 0;
     s.h_ptr.p[0] = 0;
     for (int32_t r = 0; r < nb; ++r) {
         const Request *q = batch[r];
         kb = std::max(kb, q->k);
+        longest = std::max(longest, q->nnz);
         if (q->nnz) {
             memcpy(s.h_idx.p + nnz, q->idx, (size_t)q->nnz * 4);
             memcpy(s.h_val.p + nnz, q->val, (size_t)q->nnz * 4);
@@ -167,6 +168,7 @@ bool sindi_server::launch(Slot &s, std::vector<Request *> &batch)
     s.kb = kb;
     s.pl = base;
     s.pl.k = kb;
+    s.pl.max_qnnz = longest;  // sizes the kernels' per-query LDS for this batch
     s.pl.group = std::min<int64_t>(group, nb);
     s.dq = DevQueries{nb, nnz, s.ws.q_ptr.as<int64_t>(), s.ws.q_idx.as<int32_t>(), s.ws.q_val.as<float>()};
     auto enqueue = [&]() -> sindi_status {

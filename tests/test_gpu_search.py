@@ -223,6 +223,36 @@ def test_batch_size_does_not_change_results(sindi, small, batch):
     assert (c_ids == r_ids).all() and c_sc.tobytes() == r_sc.tobytes()
 
 
+@pytest.mark.parametrize("batch", [1, 8])
+def test_long_query_in_the_call_does_not_change_results(sindi, small, batch):
+    """The kernel sizes its per-query LDS (terms merged per pass) from the longest query of
+    the call: short queries alone (64 per pass) and beside a 300-term query (512 per pass,
+    several passes per batch of 8) give bit-identical results, and the long query's own
+    results match its search alone."""
+    corpus, queries = small
+    idx = sindi.Index(corpus, alpha=0.5, window=WINDOW, tile=TILE)
+    long_q = synth.generate(1, VOCAB, nnz=("poisson", 300.0), clip=(300, 300), seed=12, stream=2)
+    assert long_q.nnz == 300
+    both = synth.Csr(np.concatenate([queries.indptr, queries.indptr[-1] + long_q.indptr[1:]]),
+                     np.concatenate([queries.indices, long_q.indices]),
+                     np.concatenate([queries.values, long_q.values]), VOCAB)
+    a_ids, a_sc = map(_np, idx.search(queries, 10, gamma=100, batch=batch))
+    b_ids, b_sc = map(_np, idx.search(both, 10, gamma=100, batch=batch))
+    n = queries.n_rows
+    assert (b_ids[:n] == a_ids).all() and b_sc[:n].tobytes() == a_sc.tobytes()
+    l_ids, l_sc = map(_np, idx.search(long_q, 10, gamma=100, batch=batch))
+    assert (b_ids[n] == l_ids[0]).all() and b_sc[n].tobytes() == l_sc[0].tobytes()
+    c_ids, c_sc = map(_np, idx.search_coarse(both, 30, batch=batch))
+    r_ids, r_sc = map(_np, idx.search_coarse(queries, 30, batch=batch))
+    assert (c_ids[:n] == r_ids).all() and c_sc[:n].tobytes() == r_sc.tobytes()
+    # the long query against the oracle's Alg. 4 on the same index
+    keep = oracle.mass_prune(corpus, 0.5)
+    oidx = oracle.build_index(corpus, WINDOW, keep)
+    o_ids, o_sc, pid, psc = oracle.approx_search(oidx, corpus, long_q, 1.0, 100, 10, want_pool=True)
+    check_same_topk(l_ids, o_ids, o_sc, _tol_kth(corpus, long_q, o_ids, o_sc, 1e-5),
+                    pool_margin=_pool_margin(pid, psc, oracle.apply_mask(corpus, keep), long_q, 1e-5))
+
+
 def test_tile_size_and_query_mix_do_not_change_results(sindi, small):
     """Sec. 3.3.1: the window split only reorders the scan; here tiles are bit-invariant,
     and a query's result does not depend on which queries share its batch."""
