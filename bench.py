@@ -138,8 +138,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index is not "
-              "sharded across GPUs in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library does "
+              "not shard the index across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import torch

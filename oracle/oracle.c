@@ -513,7 +513,7 @@ void or_approx_search(int64_t nd, int64_t window, const int64_t *iptr, const int
             const int32_t *qi = qidx + qptr[q];
             const float *qv = qval + qptr[q];
             int64_t n = qptr[q + 1] - qptr[q];
-            /* line 3: q' = beta-mass(q), kept entries in ascending term order */
+            /* beta-mass subvector of q, kept entries in ascending term order */
             mass_prune_row(qi, qv, n, beta, tmp, keep);
             int64_t np = 0;
             for (int64_t t = 0; t < n; ++t)
@@ -522,7 +522,7 @@ void or_approx_search(int64_t nd, int64_t window, const int64_t *iptr, const int
                     pv[np] = qv[t];
                     ++np;
                 }
-            /* line 4: coarse pool of gamma candidates */
+            /* coarse pool of gamma candidates (Alg. 2 over the pruned index) */
             precise_search_one(nd, window, sigma, iptr, idoc, ival, pi, pv, np, gamma, A, &h);
             int64_t nc = h.len;
             heap_to_sorted(&h, nc, cid, cs);
@@ -531,7 +531,7 @@ void or_approx_search(int64_t nd, int64_t window, const int64_t *iptr, const int
                     pool_ids[q * gamma + t] = t < nc ? cid[t] : -1;
                     pool_scores[q * gamma + t] = t < nc ? cs[t] : -INFINITY;
                 }
-            /* lines 5-11: exact rerank of every candidate, keep the best k */
+            /* exact rerank of every candidate from the unpruned rows, keep the best k */
             R.len = 0;
             for (int64_t t = 0; t < nc; ++t) {
                 int64_t i = cid[t];

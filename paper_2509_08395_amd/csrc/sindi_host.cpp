@@ -328,7 +328,7 @@ sindi_status build_device(const sindi_csr *c, const sindi_build_params *p, hipSt
                         "sindi_build: malformed corpus rows (flags 0x%x: 1 row pointers, 2 term "
                         "id range, 4 order, 8 non-finite)", ferr);
     }
-    // Alg. 3 line 3 on the device
+    // Alg. 3's pruning step on the device
     BUILD_ALLOC(keep, (size_t)nnz + 4, "keep mask");
     BUILD_ALLOC(long_rows, (size_t)nd * 4 + 4, "long-row list");
     BUILD_ALLOC(n_long, 4, "counter");
@@ -477,7 +477,7 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
         return SINDI_OK;
     }
 
-    // Alg. 3 line 3: alpha-mass subvector of every document (or the rule chosen)
+    // Alg. 3's pruning step: alpha-mass subvector of every document (or the rule chosen)
     std::vector<uint8_t> keep((size_t)c->nnz);
     parallel_for(nd, [&](int64_t lo, int64_t hi) {
         std::vector<int64_t> order;

@@ -274,7 +274,7 @@ def test_approx_reduces_to_exact_without_pruning():
 
 
 def test_approx_rerank_scores_are_exact_for_returned_ids():
-    """With pruning, every returned score is delta(x_i, q) of the unpruned row (Alg. 4 line 7),
+    """With pruning, every returned score is delta(x_i, q) of the unpruned row (Alg. 4, its exact rerank),
     and the result is the best k of the coarse pool under exact scores."""
     wl_rng = np.random.default_rng(11)
     corpus = synth.random_csr(wl_rng, 800, 100, 30)
