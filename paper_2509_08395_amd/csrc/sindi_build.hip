@@ -465,8 +465,7 @@ __global__ void k_fill_pads(const uint32_t *goff, const uint32_t *cnt, const int
 template <typename F>
 hipError_t set_lds(F *kernel, size_t bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return allow_lds(reinterpret_cast<const void *>(kernel), bytes);
 }
 
 inline unsigned blocks_for(int64_t threads, int per)

@@ -98,6 +98,12 @@ inline int entry_block(int batch, int64_t max_terms)
 // Status codes written per query slot by the finalize kernel.
 enum SlotStatus : int32_t { kSlotOk = 0, kSlotRetry = 1 };
 
+// Lets `kernel` take up to the device's per-workgroup LDS (less its static
+// LDS) as dynamic LDS, set once per device and kernel, so launches of any size
+// from several threads never lower each other's limit; fails if `bytes` is
+// beyond it.
+hipError_t allow_lds(const void *kernel, size_t bytes);
+
 // Kernel launchers (sindi_kernels.hip).  All return hipGetLastError().
 // err_flag[0]: malformed-row bits, err_flag[1]: longest well-formed row (both
 // must be zero on entry).

@@ -18,7 +18,10 @@
 
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "sindi_internal.h"
 
@@ -1247,8 +1250,7 @@ __global__ __launch_bounds__(kFinThreads) void k_score_backward(
 template <typename F>
 hipError_t set_lds(F *kernel, size_t bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return allow_lds(reinterpret_cast<const void *>(kernel), bytes);
 }
 
 template <int VT, int B, bool SAMPLE>
@@ -1296,6 +1298,30 @@ hipError_t dispatch_b(int batch, const DevIndex &ix, const DevQueries &q, const 
 }
 
 }  // namespace
+
+hipError_t allow_lds(const void *kernel, size_t bytes)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, size_t> limit;  // (device, kernel) -> bytes
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = limit.find({dev, kernel});
+    if (it == limit.end()) {
+        int max = 0;
+        hipFuncAttributes fa{};
+        if ((e = hipDeviceGetAttribute(&max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+            return e;
+        if ((e = hipFuncGetAttributes(&fa, kernel)) != hipSuccess) return e;
+        const size_t lim = (size_t)max > fa.sharedSizeBytes ? (size_t)max - fa.sharedSizeBytes : 0;
+        if ((e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim)) !=
+            hipSuccess)
+            return e;
+        it = limit.emplace(std::make_pair(dev, kernel), lim).first;
+    }
+    return bytes <= it->second ? hipSuccess : hipErrorInvalidValue;
+}
 
 hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, DevCoarse c,
                              const float *term_max, double *scratch_abs, int32_t *err_flag,
