@@ -24,6 +24,10 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden symbols; these declarations are its only
+ * exports. */
+#pragma GCC visibility push(default)
+
 typedef enum {
     SINDI_OK = 0,
     SINDI_E_INVALID = -1,  /* malformed input or parameter                     */
@@ -311,6 +315,8 @@ const char *sindi_last_error(void);
 
 /* Library version string. */
 const char *sindi_version(void);
+
+#pragma GCC visibility pop
 
 #ifdef __cplusplus
 }
