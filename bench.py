@@ -268,8 +268,9 @@ def main():
         t = time.time()
         keep = oracle.mass_prune(corpus, alpha, threads=threads)
         oidx = oracle.build_index(corpus, wl.window, keep)
-        del keep
         oracle_build_s = time.time() - t
+        pruned = oracle.apply_mask(corpus, keep) if not args.no_precision and main_leg else None
+        del keep
         t = time.time()
         oracle.approx_search(oidx, corpus, qo, wl.beta, gamma, k, threads=threads)
         oracle_s = time.time() - t
@@ -285,17 +286,35 @@ def main():
         if rec < 0.99:
             result["note"] = f"recall {rec:.4f} below 0.99"
         if not args.no_precision and main_leg:
+            dqs = sindi.DeviceCsr.from_host(qs)
             prec = {"f16": {"qps": result["value"], "ms_per_step": result["ms_per_step"],
                             "score_pass_ms": result["kernels_ms_per_step"]["accumulate_score"],
-                            "recall_at_k": result["recall_at_k"], "bytes_per_posting": 4}}
-            prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q))
+                            "recall_at_k": result["recall_at_k"], "bytes_per_posting": 4,
+                            **coarse_error(idx, dqs, qs, pruned, k)}}
+            prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q,
+                                      dqs, qs, pruned))
             result["precision"] = prec
     print(json.dumps(result), flush=True)
 
 
-def precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q, steps=3):
+def coarse_error(idx, dqs, qs, pruned, k):
+    """Relative error of the coarse scores (Alg. 2 over the index, no rerank) of the sampled
+    queries' top-k against the FP64 inner products of the pruned vectors: max and 99th
+    percentile over the returned (query, document) pairs."""
+    import oracle
+    ids, sc = idx.search_coarse(dqs, k)
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    r, c = np.nonzero(ids >= 0)
+    exact = oracle.pair_scores(pruned, qs, r, ids[r, c])
+    rel = np.abs(sc[r, c].astype(np.float64) - exact) / np.maximum(np.abs(exact), 1e-30)
+    return {"coarse_rel_err_max": float(f"{rel.max():.3g}"),
+            "coarse_rel_err_p99": float(f"{np.percentile(rel, 99):.3g}")}
+
+
+def precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q, dqs, qs, pruned,
+                  steps=3):
     """The same search with FP32 and BF16 posting values (each index built on its own):
-    throughput and Recall@k on the same sampled queries."""
+    throughput, Recall@k and coarse-score error on the same sampled queries."""
     import torch
     import oracle
     out = {}
@@ -317,7 +336,8 @@ def precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q, step
         rec = oracle.recall_at_k(ids.cpu().numpy()[rsel], truth)
         out[dt] = {"qps": round(n_q * steps / el, 1), "ms_per_step": round(1e3 * el / steps, 3),
                    "score_pass_ms": round(pr["accumulate_score"][1] / steps, 3),
-                   "recall_at_k": round(rec, 5), "bytes_per_posting": 6 if dt == "f32" else 4}
+                   "recall_at_k": round(rec, 5), "bytes_per_posting": 6 if dt == "f32" else 4,
+                   **coarse_error(idx, dqs, qs, pruned, k)}
         log(f"precision {dt}: {out[dt]}")
         idx.close()
         del idx, ids, sc
