@@ -688,6 +688,7 @@ sindi_status reserve_workspace(Workspace &ws, const Plan &pl, int64_t nq, int64_
     HIP_TRY(ws.theta.ensure((size_t)g * 4));
     HIP_TRY(ws.slot_q.ensure((size_t)g * 4));
     if (!pl.keep_all) HIP_TRY(ws.maxima.ensure((size_t)g * pl.n_max * 4));
+    if (pl.rerank) HIP_TRY(ws.pool.ensure((size_t)g * pl.need * 8));
     return SINDI_OK;
 }
 
@@ -741,8 +742,8 @@ sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
                                    ws.cand.as<uint64_t>(), ws.theta.as<float>(), pl.cap, pl.need,
-                                   pl.k, pl.rerank, pl.max_qnnz, out_ids, out_scores,
-                                   ws.status.as<int32_t>(), s);
+                                   pl.k, pl.rerank, pl.max_qnnz, ws.pool.as<uint64_t>(), out_ids,
+                                   out_scores, ws.status.as<int32_t>(), s);
         }));
     }
     return SINDI_OK;
@@ -763,6 +764,7 @@ sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
     HIP_TRY(ws.count.ensure((size_t)gsz * 4));
     HIP_TRY(ws.theta.ensure((size_t)gsz * 4));
     HIP_TRY(ws.slot_q.ensure((size_t)gsz * 4));
+    if (pl.rerank) HIP_TRY(ws.pool.ensure((size_t)gsz * pl.need * 8));
     for (size_t g0 = 0; g0 < rows.size(); g0 += (size_t)gsz) {
         const int32_t ns = (int32_t)std::min<size_t>((size_t)gsz, rows.size() - g0);
         HIP_TRY(hipMemcpyAsync(ws.slot_q.p, rows.data() + g0, (size_t)ns * 4, hipMemcpyHostToDevice, s));
@@ -776,8 +778,8 @@ sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
         HIP_TRY(timed(kProfFinal, s, [&] {
             return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
                                    ws.cand.as<uint64_t>(), nullptr, cap_all, pl.need, pl.k,
-                                   pl.rerank, pl.max_qnnz, out_ids, out_scores,
-                                   ws.status.as<int32_t>(), s);
+                                   pl.rerank, pl.max_qnnz, ws.pool.as<uint64_t>(), out_ids,
+                                   out_scores, ws.status.as<int32_t>(), s);
         }));
         HIP_TRY(hipStreamSynchronize(s));  // rows[] is pageable host memory
     }

@@ -55,7 +55,8 @@ struct DevCoarse {
 };
 
 constexpr int kAccThreads = 512;       // accumulate kernel workgroup
-constexpr int kFinThreads = 256;       // finalize / theta kernels
+constexpr int kFinThreads = 256;       // finalize, rerank and top-k kernels
+constexpr int kThetaThreads = 1024;    // threshold kernel (one radix select per query)
 constexpr int kGammaMax = 4096;        // largest reorder pool
 constexpr int kQueryHash = 8192;       // rerank hash slots (query nnz <= kQueryHash / 2)
 constexpr int kEntryBlock = 512;       // (query, term) entries merged per pass in the accumulate kernel
@@ -129,11 +130,13 @@ hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s);
 // rerank table; a longer row gets status kSlotRetry).  theta: the thresholds
 // the candidates were emitted with (null: every document was emitted); a
 // threshold <= 0 means the zero sums were left out and are supplied here.
+// With rerank, pool is scratch of n_slots * need keys (select, then rerank
+// with one wave per entry, then sort).
 hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
                            int32_t n_slots, const uint32_t *count, const uint64_t *cand,
                            const float *theta, int64_t cap, int32_t need, int32_t k, bool rerank,
-                           int32_t max_qnnz, int64_t *out_ids, float *out_scores, int32_t *status,
-                           hipStream_t s);
+                           int32_t max_qnnz, uint64_t *pool, int64_t *out_ids, float *out_scores,
+                           int32_t *status, hipStream_t s);
 
 // Device index build (sindi_build.hip); err bits: 1 row pointers, 2 term id
 // range, 4 ids not ascending, 8 non-finite, 16 a tile of more than kTileGroupsMax groups,

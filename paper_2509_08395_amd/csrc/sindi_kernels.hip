@@ -151,15 +151,27 @@ __device__ K block_select(int64_t n, int64_t r, Load load, uint32_t *hist, int *
             if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t acc = 0;
-            int d = 255;
-            for (; d > 0; --d) {
-                if (acc + (int64_t)hist[d] >= need) break;
-                acc += hist[d];
+        if (threadIdx.x < kWave) {
+            // digit of the need-th key: lane l holds digits 255 - 4l .. 252 - 4l; a prefix
+            // sum over the lanes counts the keys with larger digits
+            const int l = threadIdx.x;
+            uint32_t h[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) h[u] = hist[255 - 4 * l - u];
+            const uint32_t tot = h[0] + h[1] + h[2] + h[3];
+            uint32_t incl = tot;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(incl, d, kWave);
+                if (l >= d) incl += y;
             }
-            *s_digit = d;
-            *s_need = need - acc;
+            int64_t acc = (int64_t)(incl - tot);
+            if (acc < need && (int64_t)incl >= need) {
+                int u = 0;
+                while (u < 3 && acc + (int64_t)h[u] < need) acc += h[u++];
+                *s_digit = 255 - 4 * l - u;
+                *s_need = need - acc;
+            }
         }
         __syncthreads();
         prefix |= (K)(*s_digit) << shift;
@@ -916,7 +928,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
 // produce bitwise identical scores (integer sums), so every sampled document
 // at or above theta is kept again by the scoring pass.  The finalize kernel
 // verifies the result (at least gamma candidates kept).
-__global__ __launch_bounds__(kFinThreads) void k_theta(const float *maxima, int64_t n_m,
+__global__ __launch_bounds__(kThetaThreads) void k_theta(const float *maxima, int64_t n_m,
                                                        int64_t rank, float *theta)
 {
     __shared__ uint32_t hist[256];
@@ -1014,24 +1026,64 @@ __host__ __device__ inline int32_t pow2_at_least(int32_t n)
     return p;
 }
 
+// Sort need keys (score bits, then inverted id) in LDS descending and write
+// the first k as (id, score) to the query's output row, padded with (-1, -inf).
+__device__ void sort_and_write(uint64_t *keys, int32_t need, int32_t k, int32_t row,
+                               int64_t *out_ids, float *out_scores)
+{
+    constexpr int NT = kFinThreads;
+    const int tid = threadIdx.x;
+    const int32_t P = pow2_at_least(need);
+    for (int i = need + tid; i < P; i += NT) keys[i] = 0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += NT) {
+                const int ij = i ^ j;
+                if (ij > i) {
+                    const uint64_t x = keys[i], y = keys[ij];
+                    const bool desc = (i & kk) == 0;
+                    if (desc ? (x < y) : (x > y)) {
+                        keys[i] = y;
+                        keys[ij] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = tid; r < k; r += NT) {
+        const size_t o = (size_t)row * (size_t)k + r;
+        if (r < need) {
+            out_ids[o] = (int64_t)key_doc(keys[r]);
+            out_scores[o] = key_score(keys[r]);
+        } else {
+            out_ids[o] = -1;
+            out_scores[o] = -INFINITY;
+        }
+    }
+}
+
+// One workgroup per query slot: the exact top-need of its coarse candidates
+// (with the zero-score documents the scoring pass left implicit).  Without a
+// rerank it sorts them and writes the top k; with a rerank it writes them to
+// pool[slot][need] for k_rerank and k_topk.
 template <bool RERANK>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
-    DevIndex ix, DevQueries q, const int32_t *slot_q, const uint32_t *count, const uint64_t *cand,
-    const float *theta, int64_t cap, int32_t need, int32_t k, int32_t hlg, int32_t bm_words,
+    DevIndex ix, const int32_t *slot_q, const uint32_t *count, const uint64_t *cand,
+    const float *theta, int64_t cap, int32_t need, int32_t k, int32_t bm_words, uint64_t *pool,
     int64_t *out_ids, float *out_scores, int32_t *status)
 {
     constexpr int NT = kFinThreads, NW = NT / kWave;
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t P = pow2_at_least(need);
     uint64_t *keys = reinterpret_cast<uint64_t *>(smem);                   // [P]
-    int32_t *hid = reinterpret_cast<int32_t *>(keys + P);                   // [2^hlg]
-    float *hval = reinterpret_cast<float *>(hid + (1 << hlg));              // [2^hlg]
-    uint32_t *bm = reinterpret_cast<uint32_t *>(hval + (1 << hlg));         // [bm_words]
+    uint32_t *bm = reinterpret_cast<uint32_t *>(keys + P);                  // [bm_words]
     __shared__ uint32_t hist[256];
     __shared__ uint32_t s_n, s_wsum[NW];
     __shared__ int s_digit;
     __shared__ int64_t s_need;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x;
     const int32_t slot = blockIdx.x;
     const int32_t row = slot_q ? slot_q[slot] : slot;
     const uint32_t cnt = count[slot];
@@ -1132,51 +1184,62 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     }
 
     if (RERANK) {
-        const int64_t qa = q.indptr[row], qb = q.indptr[row + 1];
-        const int lg = hash_lg(qb - qa);
-        if (lg > hlg) {  // the launch was sized for shorter rows
-            if (tid == 0) status[row] = kSlotRetry;
-            return;
-        }
-        const QueryHash h{hid, hval, nullptr, lg};
-        build_query_hash(q, qa, qb, h);
-        for (int ci = wave; ci < need; ci += NW) {
-            const uint64_t key = keys[ci];
-            const float s = wave_dot(ix, h, key_doc(key));
-            if (lane == 0) keys[ci] = ((uint64_t)ord_f32(s) << 32) | (key & 0xFFFFFFFFull);
-        }
-        __syncthreads();
+        for (int i = tid; i < need; i += NT) pool[(size_t)slot * (size_t)need + i] = keys[i];
+        if (tid == 0) status[row] = kSlotOk;
+        return;
     }
-
-    for (int i = need + tid; i < P; i += NT) keys[i] = 0ull;
-    __syncthreads();
-    for (int kk = 2; kk <= P; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < P; i += NT) {
-                const int ij = i ^ j;
-                if (ij > i) {
-                    const uint64_t x = keys[i], y = keys[ij];
-                    const bool desc = (i & kk) == 0;
-                    if (desc ? (x < y) : (x > y)) {
-                        keys[i] = y;
-                        keys[ij] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int r = tid; r < k; r += NT) {
-        const size_t o = (size_t)row * (size_t)k + r;
-        if (r < need) {
-            out_ids[o] = (int64_t)key_doc(keys[r]);
-            out_scores[o] = key_score(keys[r]);
-        } else {
-            out_ids[o] = -1;
-            out_scores[o] = -INFINITY;
-        }
-    }
+    sort_and_write(keys, need, k, row, out_ids, out_scores);
     if (tid == 0) status[row] = kSlotOk;
+}
+
+// Exact rerank (Alg. 4): one wave per pool entry, NW entries per workgroup,
+// grid (slot, entry group); each workgroup builds the query's hash in LDS (2^hlg
+// slots).  The entry's key becomes (FP32 inner product of the unpruned row with
+// the full query, then inverted id).  Slots not finalized are skipped.
+__global__ __launch_bounds__(kFinThreads) void k_rerank(DevIndex ix, DevQueries q,
+                                                        const int32_t *slot_q, int32_t need,
+                                                        int32_t hlg, uint64_t *pool,
+                                                        int32_t *status)
+{
+    constexpr int NW = kFinThreads / kWave;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *hid = reinterpret_cast<int32_t *>(smem);          // [2^hlg]
+    float *hval = reinterpret_cast<float *>(hid + (1 << hlg));  // [2^hlg]
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int32_t slot = blockIdx.x;
+    const int32_t row = slot_q ? slot_q[slot] : slot;
+    if (status[row] != kSlotOk) return;
+    const int64_t qa = q.indptr[row], qb = q.indptr[row + 1];
+    const int lg = hash_lg(qb - qa);
+    if (lg > hlg) {  // the launch was sized for shorter rows
+        if (threadIdx.x == 0 && blockIdx.y == 0) status[row] = kSlotRetry;
+        return;
+    }
+    const QueryHash h{hid, hval, nullptr, lg};
+    build_query_hash(q, qa, qb, h);
+    const int32_t ci = (int32_t)blockIdx.y * NW + wave;
+    if (ci < need) {
+        uint64_t *e = pool + (size_t)slot * (size_t)need + ci;
+        const uint64_t key = *e;
+        const float sc = wave_dot(ix, h, key_doc(key));
+        if (lane == 0) *e = ((uint64_t)ord_f32(sc) << 32) | (key & 0xFFFFFFFFull);
+    }
+}
+
+// One workgroup per slot: sort the reranked pool and write the top k.
+__global__ __launch_bounds__(kFinThreads) void k_topk(const int32_t *slot_q, int32_t need,
+                                                      int32_t k, const uint64_t *pool,
+                                                      int64_t *out_ids, float *out_scores,
+                                                      const int32_t *status)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t *keys = reinterpret_cast<uint64_t *>(smem);  // [pow2_at_least(need)]
+    const int32_t slot = blockIdx.x;
+    const int32_t row = slot_q ? slot_q[slot] : slot;
+    if (status[row] != kSlotOk) return;
+    for (int i = threadIdx.x; i < need; i += kFinThreads)
+        keys[i] = pool[(size_t)slot * (size_t)need + i];
+    sort_and_write(keys, need, k, row, out_ids, out_scores);
 }
 
 // ------------------------------------------------------------------ pair scores
@@ -1356,7 +1419,7 @@ hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int
                         float *theta, hipStream_t s)
 {
     if (n_slots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_theta, dim3((unsigned)n_slots), dim3(kFinThreads), 0, s, maxima,
+    hipLaunchKernelGGL(k_theta, dim3((unsigned)n_slots), dim3(kThetaThreads), 0, s, maxima,
                        n_maxima, rank, theta);
     return hipGetLastError();
 }
@@ -1390,30 +1453,43 @@ hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s)
 hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_t *slot_q,
                            int32_t n_slots, const uint32_t *count, const uint64_t *cand,
                            const float *theta, int64_t cap, int32_t need, int32_t k, bool rerank,
-                           int32_t max_qnnz, int64_t *out_ids, float *out_scores, int32_t *status,
-                           hipStream_t s)
+                           int32_t max_qnnz, uint64_t *pool, int64_t *out_ids, float *out_scores,
+                           int32_t *status, hipStream_t s)
 {
     if (n_slots == 0) return hipSuccess;
-    const int32_t hlg = rerank ? hash_lg(max_qnnz > 0 ? max_qnnz : 1) : 0;
     // bitmap of candidate ids below need + cap: zero-score documents in id order
     const int64_t bm = theta ? (need + cap + 31) / 32 : 0;
     if (bm > (int64_t)1 << 20) return hipErrorInvalidValue;
-    const size_t lds = (size_t)pow2_at_least(need) * 8 + (rerank ? ((size_t)1 << hlg) * 8 : 0) +
-                       (size_t)bm * 4;
+    const size_t keys = (size_t)pow2_at_least(need) * 8;
+    const size_t lds = keys + (size_t)bm * 4;
     hipError_t e;
-    if (rerank) {
-        e = set_lds(k_finalize<true>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_finalize<true>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
-                           ix, q, slot_q, count, cand, theta, cap, need, k, hlg, (int32_t)bm,
-                           out_ids, out_scores, status);
-    } else {
+    if (!rerank) {
         e = set_lds(k_finalize<false>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_finalize<false>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s,
-                           ix, q, slot_q, count, cand, theta, cap, need, k, hlg, (int32_t)bm,
+                           ix, slot_q, count, cand, theta, cap, need, k, (int32_t)bm, nullptr,
                            out_ids, out_scores, status);
+        return hipGetLastError();
     }
+    if (!pool) return hipErrorInvalidValue;
+    e = set_lds(k_finalize<true>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize<true>, dim3((unsigned)n_slots), dim3(kFinThreads), lds, s, ix,
+                       slot_q, count, cand, theta, cap, need, k, (int32_t)bm, pool, out_ids,
+                       out_scores, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int32_t hlg = hash_lg(max_qnnz > 0 ? max_qnnz : 1);
+    const size_t lds_h = ((size_t)1 << hlg) * 8;
+    e = set_lds(k_rerank, lds_h);
+    if (e != hipSuccess) return e;
+    constexpr int NW = kFinThreads / kWave;
+    hipLaunchKernelGGL(k_rerank, dim3((unsigned)n_slots, (unsigned)((need + NW - 1) / NW)),
+                       dim3(kFinThreads), lds_h, s, ix, q, slot_q, need, hlg, pool, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = set_lds(k_topk, keys);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk, dim3((unsigned)n_slots), dim3(kFinThreads), keys, s, slot_q, need,
+                       k, pool, out_ids, out_scores, status);
     return hipGetLastError();
 }
 

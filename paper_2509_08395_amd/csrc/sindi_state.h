@@ -85,7 +85,7 @@ struct DBuf {
 // and the per-query candidate lists ("score windows" leaving LDS).
 struct Workspace {
     DBuf q_ptr, q_idx, q_val, ct, cw, cn, qinv, sabs, err, status, slot_q, maxima, theta, count,
-        cand;
+        cand, pool;
 };
 
 // The parameters of one search, resolved against the index.
@@ -98,10 +98,10 @@ struct Plan {
 };
 
 // Bytes of device scratch one query needs under a plan (candidates, maxima,
-// threshold, count, status).
+// rerank pool, threshold, count, status).
 inline size_t plan_query_bytes(const Plan &pl)
 {
-    return (size_t)pl.cap * 8 + (size_t)pl.n_max * 4 + 16;
+    return (size_t)pl.cap * 8 + (size_t)pl.n_max * 4 + (pl.rerank ? (size_t)pl.need * 8 : 0) + 16;
 }
 
 enum { kProfPrep = 0, kProfSample = 1, kProfScore = 2, kProfTheta = 3, kProfFinal = 4 };
