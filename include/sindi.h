@@ -70,7 +70,8 @@ typedef struct {
     int32_t value_dtype;     /* sindi_dtype of the stored posting values                 */
     int32_t tile;            /* max documents per on-chip score tile; 0 = library default;
                                 every window is split into equal tiles of at most this
-                                many documents; at most 16384                            */
+                                many documents; at most 16384.  A tile's lists may hold
+                                at most 2^28 - 64 groups of 4 postings (else E_INVALID)  */
     int32_t prune;           /* sindi_prune: which entries of the corpus the lists keep  */
     int32_t vn;              /* SINDI_PRUNE_VNP: entries kept per document, >= 1         */
     int64_t list_len;        /* SINDI_PRUNE_LP, _MRP_LP: entries kept per term list, >= 1 */
