@@ -50,6 +50,40 @@ def test_device_build_equals_host_build(sindi, dtype, prune, kw):
     _same_search(h, g, queries)
 
 
+def test_device_build_vocabulary_over_one_pass(sindi):
+    """A vocabulary of 100,000 terms (uniform term ids): the list counts and the ordered fill
+    each take four passes of 32,768 terms per tile."""
+    corpus = synth.generate(20_000, 100_000, nnz=("poisson", 60.0), terms=("uniform",), seed=21)
+    queries = synth.generate(24, 100_000, nnz=("poisson", 20.0), terms=("uniform",), seed=21,
+                             stream=1)
+    assert corpus.indices.max() >= 3 * 32_768
+    for dtype in ("f16", "f32"):
+        h = sindi.Index(corpus, alpha=0.5, window=10_000, value_dtype=dtype, tile=5_000)
+        g = sindi.Index(corpus, alpha=0.5, window=10_000, value_dtype=dtype, tile=5_000,
+                        gpu_build=True)
+        _same_index(h, g)
+        _same_search(h, g, queries)
+
+
+def test_device_build_degenerate_corpora(sindi):
+    """No documents, documents with no entries, and a single document: the device build
+    equals the host build, and search returns what the host-built index returns."""
+    cases = {
+        "no documents": synth.Csr(np.array([0]), np.zeros(0, np.int32), np.zeros(0, np.float32), 50),
+        "empty rows": synth.Csr(np.zeros(6, np.int64), np.zeros(0, np.int32),
+                                np.zeros(0, np.float32), 50),
+        "one document": synth.Csr(np.array([0, 3]), np.array([2, 7, 40], np.int32),
+                                  np.array([0.5, -1.5, 2.0], np.float32), 50),
+    }
+    queries = synth.Csr(np.array([0, 2, 2]), np.array([7, 40], np.int32),
+                        np.array([1.0, 0.25], np.float32), 50)
+    for name, c in cases.items():
+        h = sindi.Index(c, alpha=0.5, window=4)
+        g = sindi.Index(c, alpha=0.5, window=4, gpu_build=True)
+        _same_index(h, g)
+        _same_search(h, g, queries, k=3, gamma=3)
+
+
 def test_device_build_long_rows_signed_zeros_and_empty_rows(sindi):
     """Rows up to 3,000 entries (the one-workgroup path), negative values, explicit zeros
     (not entries) and empty rows."""
