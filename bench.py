@@ -46,10 +46,21 @@ def per_query_postings(qc, term_len):
     return int(term_len[qc.indices].sum())
 
 
+def kernel_code_sha256(path):
+    """sha256 of a source file without its comments, whitespace runs collapsed: edits to
+    comments and layout leave a counter summary of the compiled code valid."""
+    import hashlib
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"\s+", " ", src).strip()
+    return hashlib.sha256(src.encode()).hexdigest()
+
+
 def measured_traffic(config):
     """HBM bytes per scoring launch from the committed rocprofv3 counter summary, if it was
-    taken on this exact kernel source and configuration; else None."""
-    import hashlib
+    taken on this kernel code and configuration; else None."""
     src = os.path.join(ROOT, "paper_2509_08395_amd", "csrc", "sindi_kernels.hip")
     path = os.path.join(ROOT, "profiles", f"k_accumulate_{config['workload']}_{config['value_storage']}.md")
     if not os.path.exists(path):
@@ -59,10 +70,10 @@ def measured_traffic(config):
         if ":" in line and line.startswith("    "):
             key, val = line.strip().split(":", 1)
             fields[key.strip()] = val.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_code_sha256(src)
     want = (f"batch={config['batch']} tile={config['tile']} value_storage={config['value_storage']} "
             f"n_queries={config['n_queries']} n_docs={config['n_docs']}")
-    if fields.get("kernel_source_sha256") != sha or fields.get("config") != want:
+    if fields.get("kernel_code_sha256") != sha or fields.get("config") != want:
         return None
     return int(fields["fetch_bytes_per_launch"]) + int(fields["write_bytes_per_launch"])
 

@@ -7,8 +7,11 @@
 //                  emit every tile score at or above the query's threshold
 //   k_theta        per-query candidate threshold from the sampled maxima
 //   k_finalize     exact top-gamma of the emitted candidates (Alg. 2 heap
-//                  update), exact FP32 rerank from the unpruned vectors and
-//                  top-k (Alg. 4), or coarse top-k only (Alg. 2)
+//                  update): into the rerank pool, or sorted into the coarse
+//                  top-k (Alg. 2 alone)
+//   k_rerank       exact FP32 rerank of the pool from the unpruned vectors
+//                  (Alg. 4), one wave per pool entry
+//   k_topk         top-k of the reranked pool (Alg. 4)
 //   k_score_*      delta(q, x) of listed pairs (Def. 2) and its gradient
 //
 // Ranking order: score descending, then document id ascending.  A candidate
