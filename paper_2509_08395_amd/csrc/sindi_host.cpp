@@ -131,11 +131,11 @@ uint16_t to_bf16(float x)
 }
 
 // Largest tile of a window split: three 512-thread scoring workgroups (one
-// query each, of up to 256 coarse terms) still share a CU's 160 KB of LDS, and
-// fewer, larger tiles cut the per-tile work (list scan, barriers) per posting.
-// (LDS is allocated in 512-byte units; the kernel's static LDS is under 128 bytes.)
+// query each) still share a CU's 160 KB of LDS, and fewer, larger tiles cut
+// the per-tile work (list layout, barriers, read-out) per posting.  (LDS is
+// allocated in 512-byte units; the kernel's static LDS is under 128 bytes.)
 constexpr int32_t kDefaultTile = 12500;
-static_assert(3 * ((accumulate_lds_bytes(1, kDefaultTile, 256) + 128 + 511) / 512 * 512) <=
+static_assert(3 * ((accumulate_lds_bytes(1, kDefaultTile) + 128 + 511) / 512 * 512) <=
                   160 * 1024,
               "default tile too large");
 constexpr int32_t kDefaultBatch = 1;

@@ -76,11 +76,12 @@ constexpr int kFillTerms = 32768;      // list cursors per pass of the device bu
 // batch >= 2 the merged term list (ids + one weight per query, eb entries per
 // merge pass) and a region that first holds the merge sort keys, then the
 // tile's non-empty lists (first group, end, first chunk, weights).  A single
-// query keeps its terms in registers and needs neither the list nor the keys.
+// query needs its score row only: its waves lay out the tile's lists in
+// registers.
 constexpr size_t accumulate_lds_bytes(int batch, int tile_stride, int eb = kEntryBlock)
 {
+    if (batch == 1) return (size_t)tile_stride * 4;
     const size_t lists = ((size_t)3 * eb + 4) * 4 + (size_t)eb * batch * 4;
-    if (batch == 1) return (size_t)tile_stride * 4 + lists;
     const size_t merge = (size_t)eb * 12;
     return (size_t)batch * tile_stride * 4 + (size_t)eb * 4 + (size_t)eb * batch * 4 +
            (merge > lists ? merge : lists);

@@ -1,10 +1,12 @@
 // gfx950 kernels of the SINDI search path (arXiv 2509.08395).
 //
 //   k_query_prep   validate query rows; beta-mass subvector (Def. 6, Sec. 4.1)
-//   k_accumulate   stream each query term's window list I_{j,w} (Alg. 2,
-//                  product + accumulate steps) into on-chip score tiles;
-//                  then either sample per-thread maxima (threshold pass) or
-//                  emit every tile score at or above the query's threshold
+//   k_accumulate1  stream each query term's window list I_{j,w} (Alg. 2,
+//                  product + accumulate steps) into an on-chip score tile,
+//                  one query per workgroup; then either sample per-thread
+//                  maxima (threshold pass) or emit every tile score at or
+//                  above the query's threshold
+//   k_accumulate   the same for batches of 2, 4 or 8 queries sharing lists
 //   k_theta        per-query candidate threshold from the sampled maxima
 //   k_finalize     exact top-gamma of the emitted candidates (Alg. 2 heap
 //                  update): into the rerank pool, or sorted into the coarse
@@ -386,31 +388,6 @@ template <> struct Val<2> {  // BF16
     }
 };
 
-template <int B> struct Weights {
-    static __device__ __forceinline__ void read(const float *w, float (&o)[B])
-    {
-#pragma unroll
-        for (int b = 0; b < B; b += 4) {
-            const float4 x = *reinterpret_cast<const float4 *>(w + b);
-            o[b] = x.x;
-            o[b + 1] = x.y;
-            o[b + 2] = x.z;
-            o[b + 3] = x.w;
-        }
-    }
-};
-template <> struct Weights<1> {
-    static __device__ __forceinline__ void read(const float *w, float (&o)[1]) { o[0] = w[0]; }
-};
-template <> struct Weights<2> {
-    static __device__ __forceinline__ void read(const float *w, float (&o)[2])
-    {
-        const float2 x = *reinterpret_cast<const float2 *>(w);
-        o[0] = x.x;
-        o[1] = x.y;
-    }
-};
-
 // Emit the scores of one query row segment that reach the threshold: each
 // lane holds NV scores of consecutive documents starting at m0.
 template <int NV>
@@ -463,7 +440,7 @@ __device__ __forceinline__ void unpack_pair(uint32_t wlo, uint32_t whi, int32_t 
     h = (int32_t)(whi + (l < 0 ? 1u : 0u));
 }
 
-// One workgroup = a batch of B query slots x a contiguous run of tiles.  The
+// One workgroup = a batch of B >= 2 query slots x a contiguous run of tiles.  The
 // batch's (query, term) entries are first merged into one ascending list of
 // distinct terms, each with a weight per query (zero where the query lacks
 // the term), so a list I_{term, tile} shared by several queries of the batch
@@ -496,19 +473,18 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
 {
     constexpr int NT = kAccThreads, NW = NT / kWave;
     const int EB = eb;  // entries merged per pass: a power of two, at most NT
-    constexpr bool PACK = B >= 2;
-    constexpr int NP = PACK ? B / 2 : 1;  // score words per document
-    constexpr int KU = VT == 0 ? 4 : 8;   // chunks in flight per wave
+    constexpr int NP = B / 2;            // score words per document
+    constexpr int KU = VT == 0 ? 4 : 8;  // chunks in flight per wave
+    static_assert(B >= 2 && B % 2 == 0, "one query per workgroup runs in k_accumulate1");
     static_assert(kEntryBlock <= NT, "at most one merged entry per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = ix.tile_stride;
-    // PACK: uint64 [NP][T]; else int32 [T].  Both are B * T * 4 bytes.
+    // score rows: uint64 [NP][T], B * T * 4 bytes
     unsigned char *A = smem;
-    // B >= 2: the merged term list (u_term / u_w, EB entries); one query keeps
-    // its terms in registers instead (my_term / my_w, one per thread)
+    // the merged term list (u_term / u_w, EB entries)
     int32_t *u_term = reinterpret_cast<int32_t *>(smem + (size_t)B * T * 4);
-    float *u_w = reinterpret_cast<float *>(u_term + (B == 1 ? 0 : EB));  // [EB][B]
-    unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (B == 1 ? 0 : (size_t)EB * B));
+    float *u_w = reinterpret_cast<float *>(u_term + EB);  // [EB][B]
+    unsigned char *region = reinterpret_cast<unsigned char *>(u_w + (size_t)EB * B);
     uint64_t *keys = reinterpret_cast<uint64_t *>(region);                 // merge phase
     uint32_t *flag = reinterpret_cast<uint32_t *>(keys + EB);              // merge phase
     uint32_t *l_base = reinterpret_cast<uint32_t *>(region);               // tile phase
@@ -564,19 +540,8 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     const int32_t n_blocks = (n_e + EB - 1) / EB;
 
     // Merge entries [e0, e0 + EB) of the batch into u_term / u_w (s_nu terms).
-    int32_t my_term = 0;
-    float my_w = 0.0f;
     auto merge = [&](int32_t e0) {
         const int32_t ne = min(EB, n_e - e0);
-        if (B == 1) {  // one query: its coarse terms are already ascending and distinct
-            if (tid < ne) {
-                my_term = c.ct[s_qa[0] + e0 + tid];
-                my_w = c.cw[s_qa[0] + e0 + tid];
-            }
-            if (tid == 0) s_nu = ne;
-            __syncthreads();
-            return;
-        }
         int P = 1;
         while (P < ne) P <<= 1;
         if (tid < P) {
@@ -660,7 +625,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
             // with the index of their first chunk
             uint32_t gs = 0, ng = 0;
             if (tid < nu) {
-                const int32_t term = B == 1 ? my_term : u_term[tid];
+                const int32_t term = u_term[tid];
                 const uint32_t lo = have_pre ? pre_lo : toff[term];
                 const uint32_t hi = have_pre ? pre_hi : toff[term + 1];
                 gs = lo & kGoffMask;
@@ -679,7 +644,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                 l_end[li] = gs + ng;
                 l_cp[li] = ex & 0xFFFFFu;
 #pragma unroll
-                for (int b = 0; b < B; ++b) l_w[li * B + b] = B == 1 ? my_w : u_w[tid * B + b];
+                for (int b = 0; b < B; ++b) l_w[li * B + b] = u_w[tid * B + b];
             }
             const uint32_t n_list = total >> 20, n_chunk = total & 0xFFFFFu;
             if (tid == 0) l_cp[n_list] = n_chunk;
@@ -700,7 +665,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     if (tid < nu) {
                         const int64_t t2 = SAMPLE ? (tn * ix.n_tiles / n_sample) : tn;
                         const uint32_t *toff2 = ix.term_goff + (size_t)t2 * (size_t)(ix.n_cols + 1);
-                        const int32_t term = B == 1 ? my_term : u_term[tid];
+                        const int32_t term = u_term[tid];
                         pre_lo = toff2[term];
                         pre_hi = toff2[term + 1];
                     }
@@ -777,31 +742,24 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                             // byte offsets of the documents' 32-bit score words
                             const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16,
                                                     ids[i].y & 0xFFFFu, ids[i].y >> 16};
-                            if (PACK) {
-                                float v[4];
-                                Val<VT>::decode(raw[i], v);
-                                unsigned char *A8 = A;
+                            float v[4];
+                            Val<VT>::decode(raw[i], v);
+                            unsigned char *A8 = A;
 #pragma unroll
-                                for (int qp = 0; qp < NP; ++qp) {
-                                    const float w0 = w[2 * qp], w1 = w[2 * qp + 1];
-                                    if (w0 == 0.0f && w1 == 0.0f) continue;
+                            for (int qp = 0; qp < NP; ++qp) {
+                                const float w0 = w[2 * qp], w1 = w[2 * qp + 1];
+                                if (w0 == 0.0f && w1 == 0.0f) continue;
 #pragma unroll
-                                    for (int p = 0; p < 4; ++p) {
-                                        const int32_t lo = (int32_t)(w0 * v[p]);
-                                        const int32_t hi = (int32_t)(w1 * v[p]);
-                                        const uint32_t hw = (uint32_t)hi + (uint32_t)(lo >> 31);
-                                        const uint64_t add = ((uint64_t)hw << 32) | (uint32_t)lo;
-                                        uint64_t *dst = reinterpret_cast<uint64_t *>(
-                                            A8 + (size_t)qp * T * 8 + 2u * d4[p]);
-                                        __hip_atomic_fetch_add(dst, add, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                                    }
+                                for (int p = 0; p < 4; ++p) {
+                                    const int32_t lo = (int32_t)(w0 * v[p]);
+                                    const int32_t hi = (int32_t)(w1 * v[p]);
+                                    const uint32_t hw = (uint32_t)hi + (uint32_t)(lo >> 31);
+                                    const uint64_t add = ((uint64_t)hw << 32) | (uint32_t)lo;
+                                    uint64_t *dst = reinterpret_cast<uint64_t *>(
+                                        A8 + (size_t)qp * T * 8 + 2u * d4[p]);
+                                    __hip_atomic_fetch_add(dst, add, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                                 }
-                            } else {
-#pragma unroll
-                                for (int p = 0; p < 4; ++p)
-                                    lds_add_i32(reinterpret_cast<int32_t *>(A + d4[p]),
-                                                (int32_t)Val<VT>::prod(raw[i], p, w[0]));
                             }
                         }
                     }
@@ -816,111 +774,318 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
         // ---- read the rows: sample maxima or emit every score at or above the
         // query's threshold, compared as the integer sum against the smallest sum
         // that reaches the threshold
-        if (PACK) {
-            uint64_t *A64 = reinterpret_cast<uint64_t *>(A);
-            for (int qp = 0; qp < NP; ++qp) {
-                const int32_t sl0 = s_slot[2 * qp], sl1 = s_slot[2 * qp + 1];
-                const bool any0 = sl0 >= 0 && (SAMPLE || !s_none[2 * qp]);
-                const bool any1 = sl1 >= 0 && (SAMPLE || !s_none[2 * qp + 1]);
-                uint64_t *row = A64 + (size_t)qp * T;
-                if (!any0 && !any1) {
-                    for (int m = tid * 2; m < len; m += NT * 2)
-                        *reinterpret_cast<int4 *>(row + m) = fresh_zero4();
-                    continue;
-                }
-                const float qi0 = s_qinv[2 * qp], qi1 = s_qinv[2 * qp + 1];
-                if (SAMPLE) {
-                    int32_t m0 = INT32_MIN, m1 = INT32_MIN;
-                    for (int m = tid; m < len; m += NT) {
-                        const uint64_t wd = row[m];
-                        row[m] = 0ull;
-                        int32_t l, h;
-                        unpack_pair((uint32_t)wd, (uint32_t)(wd >> 32), l, h);
-                        m0 = max(m0, l);
-                        m1 = max(m1, h);
-                    }
-                    if (sl0 >= 0)
-                        maxima[((size_t)sl0 * n_sample + ti) * NT + tid] = tid < len ? (float)m0 * qi0 : -INFINITY;
-                    if (sl1 >= 0)
-                        maxima[((size_t)sl1 * n_sample + ti) * NT + tid] = tid < len ? (float)m1 * qi1 : -INFINITY;
-                } else {
-                    const int32_t th0 = s_thr[2 * qp], th1 = s_thr[2 * qp + 1];
-                    const bool imp0 = s_imp[2 * qp], imp1 = s_imp[2 * qp + 1];
-                    for (int base = wave * 128; base < len; base += NW * 128) {
-                        const int m0 = base + lane * 2;
-                        int4 r = make_int4(0, 0, 0, 0);
-                        if (m0 < len) {
-                            r = *reinterpret_cast<const int4 *>(row + m0);
-                            *reinterpret_cast<int4 *>(row + m0) = fresh_zero4();
-                        }
-                        int32_t l0, h0, l1, h1;
-                        unpack_pair((uint32_t)r.x, (uint32_t)r.y, l0, h0);
-                        unpack_pair((uint32_t)r.z, (uint32_t)r.w, l1, h1);
-                        const bool oa[2] = {any0 && m0 < len && l0 >= th0 && (!imp0 || l0 != 0),
-                                            any0 && m0 + 1 < len && l1 >= th0 && (!imp0 || l1 != 0)};
-                        const bool ob[2] = {any1 && m0 < len && h0 >= th1 && (!imp1 || h0 != 0),
-                                            any1 && m0 + 1 < len && h1 >= th1 && (!imp1 || h1 != 0)};
-                        if (__ballot(oa[0] || oa[1] || ob[0] || ob[1]) == 0) continue;
-                        const float a[2] = {(float)l0 * qi0, (float)l1 * qi0};
-                        const float b2[2] = {(float)h0 * qi1, (float)h1 * qi1};
-                        if (sl0 >= 0)
-                            emit_candidates<2>(a, oa, d0 + m0, count + sl0, cand + (size_t)sl0 * cap, cap);
-                        if (sl1 >= 0)
-                            emit_candidates<2>(b2, ob, d0 + m0, count + sl1, cand + (size_t)sl1 * cap, cap);
-                    }
-                }
+        uint64_t *A64 = reinterpret_cast<uint64_t *>(A);
+        for (int qp = 0; qp < NP; ++qp) {
+            const int32_t sl0 = s_slot[2 * qp], sl1 = s_slot[2 * qp + 1];
+            const bool any0 = sl0 >= 0 && (SAMPLE || !s_none[2 * qp]);
+            const bool any1 = sl1 >= 0 && (SAMPLE || !s_none[2 * qp + 1]);
+            uint64_t *row = A64 + (size_t)qp * T;
+            if (!any0 && !any1) {
+                for (int m = tid * 2; m < len; m += NT * 2)
+                    *reinterpret_cast<int4 *>(row + m) = fresh_zero4();
+                continue;
             }
-        } else {
-            int32_t *A32 = reinterpret_cast<int32_t *>(A);
-            const int32_t slot = s_slot[0];
-            if (slot < 0 || (!SAMPLE && s_none[0])) {
-                for (int m = tid * 4; m < len; m += NT * 4)
-                    *reinterpret_cast<int4 *>(A32 + m) = fresh_zero4();
+            const float qi0 = s_qinv[2 * qp], qi1 = s_qinv[2 * qp + 1];
+            if (SAMPLE) {
+                int32_t m0 = INT32_MIN, m1 = INT32_MIN;
+                for (int m = tid; m < len; m += NT) {
+                    const uint64_t wd = row[m];
+                    row[m] = 0ull;
+                    int32_t l, h;
+                    unpack_pair((uint32_t)wd, (uint32_t)(wd >> 32), l, h);
+                    m0 = max(m0, l);
+                    m1 = max(m1, h);
+                }
+                if (sl0 >= 0)
+                    maxima[((size_t)sl0 * n_sample + ti) * NT + tid] = tid < len ? (float)m0 * qi0 : -INFINITY;
+                if (sl1 >= 0)
+                    maxima[((size_t)sl1 * n_sample + ti) * NT + tid] = tid < len ? (float)m1 * qi1 : -INFINITY;
             } else {
-                const float qinv = s_qinv[0];
-                if (SAMPLE) {
-                    int32_t mx = INT32_MIN;
-                    for (int m = tid; m < len; m += NT) {
-                        mx = max(mx, A32[m]);
-                        A32[m] = 0;
+                const int32_t th0 = s_thr[2 * qp], th1 = s_thr[2 * qp + 1];
+                const bool imp0 = s_imp[2 * qp], imp1 = s_imp[2 * qp + 1];
+                for (int base = wave * 128; base < len; base += NW * 128) {
+                    const int m0 = base + lane * 2;
+                    int4 r = make_int4(0, 0, 0, 0);
+                    if (m0 < len) {
+                        r = *reinterpret_cast<const int4 *>(row + m0);
+                        *reinterpret_cast<int4 *>(row + m0) = fresh_zero4();
                     }
-                    maxima[((size_t)slot * n_sample + ti) * NT + tid] = tid < len ? (float)mx * qinv : -INFINITY;
-                } else {
-                    const int32_t th = s_thr[0];
-                    // With a threshold <= 0 the zero sums (most documents) are left out
-                    // and the finalize kernel supplies them in id order; then any nonzero
-                    // word needs a look.  Otherwise a word needs a look if its largest
-                    // sum reaches the threshold.  Lanes past the row end read 0.
-                    // The two cases are separate loops (IMP a compile-time flag).
-                    auto read_out = [&](auto imp_c) {
-                        constexpr bool IMP = decltype(imp_c)::value;
-                        for (int base = wave * 256; base < len; base += NW * 256) {
-                            const int m0 = base + lane * 4;
-                            int4 r = make_int4(0, 0, 0, 0);
-                            if (m0 < len) {
-                                r = *reinterpret_cast<const int4 *>(A32 + m0);
-                                *reinterpret_cast<int4 *>(A32 + m0) = fresh_zero4();
-                            }
-                            const bool look = IMP ? ((r.x | r.y | r.z | r.w) != 0)
-                                                  : max(max(r.x, r.y), max(r.z, r.w)) >= th;
-                            if (__ballot(look) == 0) continue;  // the common case
-                            bool ok[4];
-                            ok[0] = r.x >= th && (!IMP || r.x != 0) && m0 < len;
-                            ok[1] = r.y >= th && (!IMP || r.y != 0) && m0 + 1 < len;
-                            ok[2] = r.z >= th && (!IMP || r.z != 0) && m0 + 2 < len;
-                            ok[3] = r.w >= th && (!IMP || r.w != 0) && m0 + 3 < len;
-                            const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv,
-                                                 (float)r.z * qinv, (float)r.w * qinv};
-                            emit_candidates<4>(sv, ok, d0 + m0, count + slot,
-                                               cand + (size_t)slot * cap, cap);
-                        }
-                    };
-                    if (s_imp[0])
-                        read_out(std::true_type{});
-                    else
-                        read_out(std::false_type{});
+                    int32_t l0, h0, l1, h1;
+                    unpack_pair((uint32_t)r.x, (uint32_t)r.y, l0, h0);
+                    unpack_pair((uint32_t)r.z, (uint32_t)r.w, l1, h1);
+                    const bool oa[2] = {any0 && m0 < len && l0 >= th0 && (!imp0 || l0 != 0),
+                                        any0 && m0 + 1 < len && l1 >= th0 && (!imp0 || l1 != 0)};
+                    const bool ob[2] = {any1 && m0 < len && h0 >= th1 && (!imp1 || h0 != 0),
+                                        any1 && m0 + 1 < len && h1 >= th1 && (!imp1 || h1 != 0)};
+                    if (__ballot(oa[0] || oa[1] || ob[0] || ob[1]) == 0) continue;
+                    const float a[2] = {(float)l0 * qi0, (float)l1 * qi0};
+                    const float b2[2] = {(float)h0 * qi1, (float)h1 * qi1};
+                    if (sl0 >= 0)
+                        emit_candidates<2>(a, oa, d0 + m0, count + sl0, cand + (size_t)sl0 * cap, cap);
+                    if (sl1 >= 0)
+                        emit_candidates<2>(b2, ob, d0 + m0, count + sl1, cand + (size_t)sl1 * cap, cap);
                 }
             }
+        }
+        __syncthreads();
+    }
+}
+
+// Inclusive prefix sum over the wave in lane order: within each row of 16
+// lanes by four shifted adds (DPP row_shr 1, 2, 4, 8; lanes shifted in from
+// outside the row read 0), then each row adds the totals of the rows below.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 47);
+    return x + (lane >= 16 ? r0 : 0u) + (lane >= 32 ? r1 : 0u) + (lane >= 48 ? r2 : 0u);
+}
+
+// The single-query form of k_accumulate (same grid, same scores, same
+// read-out).  Every wave lays out the tile's chunks itself: the query's terms
+// are taken 64 at a time (a segment, one list per lane), a wave-wide prefix
+// sum over the lists' chunk counts numbers the chunks, and the wave keeps its
+// contiguous share of the tile's chunks.  The chunk layout thus needs no LDS
+// table and no barrier: a tile costs the two barriers around its read-out.
+// The first segment's terms, weights and list bounds (the next tile's
+// prefetched during the current one) stay in registers; further segments
+// are reloaded (cache hits) where used.
+template <int VT, bool SAMPLE>
+__global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_accumulate1(
+    DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
+    int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
+    int64_t cap, int32_t tiles_per_wg)
+{
+    constexpr int NT = kAccThreads, NW = NT / kWave;
+    constexpr int KU = VT == 0 ? 4 : 8;  // chunks in flight per wave
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *A32 = reinterpret_cast<int32_t *>(smem);  // the query's score row [tile_stride]
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = (int)uni((uint32_t)tid / kWave);
+    const int32_t slot = blockIdx.x;  // one workgroup per query slot: slot < n_slots
+    const int32_t row = slot_q[slot];
+    const int64_t qa = q.indptr[row];
+    const int32_t n = c.cn[row];
+    const float qinv = c.qinv[row];
+    int32_t th = 0;
+    bool none = false, imp = false;
+    if (!SAMPLE) {
+        const int64_t a = sum_threshold(theta[slot], qinv);
+        none = a > INT32_MAX;
+        th = none ? INT32_MAX : (int32_t)a;
+        const float tv = theta[slot];
+        imp = tv <= 0.0f && tv != -INFINITY;
+    }
+    const int32_t nseg = (n + kWave - 1) / kWave;
+    const int32_t term0 = lane < n ? c.ct[qa + lane] : 0;
+    const float w0 = lane < n ? c.cw[qa + lane] : 0.0f;
+    using Raw = typename Val<VT>::Raw;
+    const int64_t n_tile_iter = SAMPLE ? n_sample : ix.n_tiles;
+    const int64_t ti_beg = (int64_t)blockIdx.y * tiles_per_wg;
+    const int64_t ti_end = min(n_tile_iter, ti_beg + tiles_per_wg);
+    const size_t toff_stride = (size_t)(ix.n_cols + 1);
+    auto tile_of = [&](int64_t ti) { return SAMPLE ? (ti * ix.n_tiles / n_sample) : ti; };
+
+    // the score row starts cleared; reading a tile's row clears it again
+    {
+        int4 *A4 = reinterpret_cast<int4 *>(smem);
+        for (int i = tid; i < ix.tile_stride / 4; i += NT) A4[i] = make_int4(0, 0, 0, 0);
+    }
+    // Bounds of the first segment's lists in the tile (the next tile's are
+    // loaded during the current one; every lane loads, lanes past the query's
+    // terms read term 0's bounds and ignore them).  The grid gives every
+    // workgroup at least one tile.
+    uint32_t pre_lo, pre_hi;
+    {
+        const uint32_t *toff = ix.term_goff + (size_t)tile_of(ti_beg) * toff_stride;
+        pre_lo = toff[term0];
+        pre_hi = toff[term0 + 1];
+    }
+    // The run's tiles, one per lane (reloaded every 64 tiles): first document,
+    // length, first 4-posting group and group count, so a tile starts without
+    // waiting for memory.
+    int64_t r_d0 = 0;
+    uint64_t r_g0 = 0;
+    int32_t r_len = 0;
+    uint32_t r_ng = 0;
+    int64_t r_base = ti_beg;
+    auto load_run = [&](int64_t base) {
+        const int64_t ti = base + lane;
+        if (ti < ti_end) {
+            const int64_t t = tile_of(ti);
+            r_d0 = ix.tile_doc[t];
+            r_len = (int32_t)(ix.tile_doc[t + 1] - r_d0);
+            const int64_t p0 = ix.tile_post[t];
+            r_g0 = (uint64_t)p0 >> 2;
+            r_ng = (uint32_t)((ix.tile_post[t + 1] - p0) >> 2);
+        }
+    };
+    load_run(r_base);
+    __syncthreads();
+
+    for (int64_t ti = ti_beg; ti < ti_end; ++ti) {
+        if (ti - r_base == kWave) {
+            r_base = ti;
+            load_run(r_base);
+        }
+        const int j = (int)(ti - r_base);
+        const int64_t t = tile_of(ti);
+        const int64_t d0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(r_d0 >> 32), j) << 32) |
+                                     (uint32_t)__builtin_amdgcn_readlane((int)r_d0, j));
+        const int32_t len = __builtin_amdgcn_readlane(r_len, j);
+        const uint64_t G0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(r_g0 >> 32), j) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)r_g0, j);
+        const uint32_t n_groups = (uint32_t)__builtin_amdgcn_readlane((int)r_ng, j);
+        const uint32_t *toff = ix.term_goff + (size_t)t * toff_stride;
+        const uint32_t gs0 = pre_lo & kGoffMask;
+        const uint32_t ng0 = lane < n ? (pre_hi & kGoffMask) - gs0 : 0u;
+        {
+            const int64_t tn = ti + 1 < ti_end ? ti + 1 : ti;
+            const uint32_t *toff2 = ix.term_goff + (size_t)tile_of(tn) * toff_stride;
+            pre_lo = toff2[term0];
+            pre_hi = toff2[term0 + 1];
+        }
+        // segment s >= 1: lane l holds list 64 s + l
+        auto segment = [&](int32_t s, uint32_t &gs, uint32_t &ng, float &w) {
+            gs = 0;
+            ng = 0;
+            w = 0.0f;
+            const int32_t li = s * kWave + lane;
+            if (li < n) {
+                const int32_t term = c.ct[qa + li];
+                w = c.cw[qa + li];
+                const uint32_t lo = toff[term], hi = toff[term + 1];
+                gs = lo & kGoffMask;
+                ng = (hi & kGoffMask) - gs;
+            }
+        };
+        // chunk numbers: list l of a segment holds its chunks [incl - nch, incl)
+        const uint32_t incl0 = wave_incl_scan((ng0 + kChunk - 1) / kChunk);
+        uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl0, kWave - 1);
+        for (int32_t s = 1; s < nseg; ++s) {
+            uint32_t gs, ng;
+            float w;
+            segment(s, gs, ng, w);
+            total += (uint32_t)__builtin_amdgcn_readlane(
+                (int)wave_incl_scan((ng + kChunk - 1) / kChunk), kWave - 1);
+        }
+        const uint32_t c_beg = uni((uint32_t)(((uint64_t)total * (uint32_t)wave) / NW));
+        const uint32_t c_end = uni((uint32_t)(((uint64_t)total * (uint32_t)(wave + 1)) / NW));
+        // the tile's groups, addressed by 32-bit byte offsets (a tile holds at most
+        // kTileGroupsMax groups; the arrays end with kTailSlots zero postings)
+        const gbytes pd_t =
+            uni_ptr(reinterpret_cast<const unsigned char *>(ix.post_doc) + G0 * sizeof(uint2));
+        const gbytes pv_t =
+            uni_ptr(reinterpret_cast<const unsigned char *>(ix.post_val) + G0 * sizeof(Raw));
+        uint32_t off = 0;  // chunks of the segments before s
+        for (int32_t s = 0; s < nseg && off < c_end; ++s) {
+            uint32_t gs = gs0, ng = ng0, incl = incl0;
+            float wl = w0;
+            if (s > 0) {
+                segment(s, gs, ng, wl);
+                incl = wave_incl_scan((ng + kChunk - 1) / kChunk);
+            }
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+            const uint32_t la = max(c_beg, off) - off, lb = min(c_end, off + st) - off;
+            off += st;
+            if (la >= lb || off <= c_beg) continue;
+            // list of chunk ci: the lanes whose lists end at or before ci, counted
+            const uint32_t cpn = incl;
+            const uint32_t basel = gs - (incl - (ng + kChunk - 1) / kChunk) * (uint32_t)kChunk;
+            const uint32_t endl = gs + ng;
+            for (uint32_t cs = la; cs < lb; cs += KU) {
+                uint2 ids[KU];
+                Raw raw[KU];
+                uint32_t nl[KU];
+                int32_t kl[KU];
+                // Loads are unconditional, so they leave back to back: lane l reads
+                // group g0 + l even past its chunk's end (at most 63 groups past the
+                // tile's last group: inside the arrays); those lanes add nothing.
+#pragma unroll
+                for (int i = 0; i < KU; ++i) {
+                    const uint32_t ci = cs + (uint32_t)i;
+                    uint32_t g0 = 0, nn = 0;
+                    int32_t k = 0;
+                    if (ci < lb) {  // wave-uniform
+                        k = (int32_t)__popcll(__ballot(cpn <= ci));
+                        g0 = (uint32_t)__builtin_amdgcn_readlane((int)basel, k) + ci * (uint32_t)kChunk;
+                        nn = min((uint32_t)kChunk,
+                                 (uint32_t)__builtin_amdgcn_readlane((int)endl, k) - g0);
+                        g0 = min(g0, n_groups);
+                    }
+                    kl[i] = k;
+                    nl[i] = nn;
+                    const uint32_t gi = g0 + (uint32_t)lane;
+                    load_at(pd_t, gi * (uint32_t)sizeof(uint2), ids[i]);
+                    load_at(pv_t, gi * (uint32_t)sizeof(Raw), raw[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < KU; ++i) {
+                    if ((uint32_t)lane >= nl[i]) continue;
+                    const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl), kl[i]));
+                    // byte offsets of the documents' 32-bit score words
+                    const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16, ids[i].y & 0xFFFFu,
+                                            ids[i].y >> 16};
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+                        lds_add_i32(reinterpret_cast<int32_t *>(smem + d4[p]),
+                                    (int32_t)Val<VT>::prod(raw[i], p, w));
+                }
+                // Every slot's loads are complete here, also those of slots that
+                // added nothing: no load of this batch is then still in flight when
+                // the next batch (or the next tile's first, behind the list-bounds
+                // prefetch) reuses its registers, so those loads never wait.
+#pragma unroll
+                for (int i = 0; i < KU; ++i) __asm__ volatile("" ::"v"(ids[i].x), "v"(raw[i].x));
+            }
+        }
+        __syncthreads();
+
+        // ---- read the row: sample maxima or emit every score at or above the
+        // query's threshold (as in k_accumulate)
+        if (!SAMPLE && none) {
+            for (int m = tid * 4; m < len; m += NT * 4)
+                *reinterpret_cast<int4 *>(A32 + m) = fresh_zero4();
+        } else if (SAMPLE) {
+            int32_t mx = INT32_MIN;
+            for (int m = tid; m < len; m += NT) {
+                mx = max(mx, A32[m]);
+                A32[m] = 0;
+            }
+            maxima[((size_t)slot * n_sample + ti) * NT + tid] = tid < len ? (float)mx * qinv : -INFINITY;
+        } else {
+            auto read_out = [&](auto imp_c) {
+                constexpr bool IMP = decltype(imp_c)::value;
+                for (int base = wave * 256; base < len; base += NW * 256) {
+                    const int m0 = base + lane * 4;
+                    int4 r = make_int4(0, 0, 0, 0);
+                    if (m0 < len) {
+                        r = *reinterpret_cast<const int4 *>(A32 + m0);
+                        *reinterpret_cast<int4 *>(A32 + m0) = fresh_zero4();
+                    }
+                    const bool look = IMP ? ((r.x | r.y | r.z | r.w) != 0)
+                                          : max(max(r.x, r.y), max(r.z, r.w)) >= th;
+                    if (__ballot(look) == 0) continue;  // the common case
+                    bool ok[4];
+                    ok[0] = r.x >= th && (!IMP || r.x != 0) && m0 < len;
+                    ok[1] = r.y >= th && (!IMP || r.y != 0) && m0 + 1 < len;
+                    ok[2] = r.z >= th && (!IMP || r.z != 0) && m0 + 2 < len;
+                    ok[3] = r.w >= th && (!IMP || r.w != 0) && m0 + 3 < len;
+                    const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv, (float)r.z * qinv,
+                                         (float)r.w * qinv};
+                    emit_candidates<4>(sv, ok, d0 + m0, count + slot, cand + (size_t)slot * cap, cap);
+                }
+            };
+            if (imp)
+                read_out(std::true_type{});
+            else
+                read_out(std::false_type{});
         }
         __syncthreads();
     }
@@ -1327,7 +1492,11 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
 {
     const int eb = entry_block(B, max_terms);
     const size_t lds = accumulate_lds_bytes(B, ix.tile_stride, eb);
-    hipError_t e = set_lds(k_accumulate<VT, B, SAMPLE>, lds);
+    hipError_t e;
+    if constexpr (B == 1)
+        e = set_lds(k_accumulate1<VT, SAMPLE>, lds);
+    else
+        e = set_lds(k_accumulate<VT, B, SAMPLE>, lds);
     if (e != hipSuccess) return e;
     const int64_t n_batches = (n_slots + B - 1) / B;
     const int64_t n_iter = SAMPLE ? n_sample : ix.n_tiles;
@@ -1342,9 +1511,14 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
         groups = (n_iter + per - 1) / per;
     }
     dim3 grid((unsigned)n_batches, (unsigned)groups);
-    hipLaunchKernelGGL((k_accumulate<VT, B, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
-                       slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, (int32_t)per,
-                       (int32_t)eb);
+    if constexpr (B == 1) {
+        hipLaunchKernelGGL((k_accumulate1<VT, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
+                           slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, (int32_t)per);
+    } else {
+        hipLaunchKernelGGL((k_accumulate<VT, B, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
+                           slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, (int32_t)per,
+                           (int32_t)eb);
+    }
     return hipGetLastError();
 }
 

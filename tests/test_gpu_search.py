@@ -225,10 +225,11 @@ def test_batch_size_does_not_change_results(sindi, small, batch):
 
 @pytest.mark.parametrize("batch", [1, 8])
 def test_long_query_in_the_call_does_not_change_results(sindi, small, batch):
-    """The kernel sizes its per-query LDS (terms merged per pass) from the longest query of
-    the call: short queries alone (64 per pass) and beside a 300-term query (512 per pass,
-    several passes per batch of 8) give bit-identical results, and the long query's own
-    results match its search alone."""
+    """A 300-term query beside short ones changes nothing: one query per workgroup lays out
+    its terms 64 per segment (five segments for the long query), and a batch of 8 sizes its
+    LDS (terms merged per pass) from the longest query of the call (64 per pass for short
+    queries alone, 512 and several passes beside the long one).  Results are bit-identical,
+    and the long query's own results match its search alone."""
     corpus, queries = small
     idx = sindi.Index(corpus, alpha=0.5, window=WINDOW, tile=TILE)
     long_q = synth.generate(1, VOCAB, nnz=("poisson", 300.0), clip=(300, 300), seed=12, stream=2)
