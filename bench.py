@@ -62,7 +62,7 @@ def measured_traffic(config):
     """HBM bytes per scoring launch from the committed rocprofv3 counter summary, if it was
     taken on this kernel code and configuration; else None."""
     src = os.path.join(ROOT, "paper_2509_08395_amd", "csrc", "sindi_kernels.hip")
-    path = os.path.join(ROOT, "profiles", f"k_accumulate_{config['workload']}_{config['value_storage']}.md")
+    path = os.path.join(ROOT, "profiles", f"k_accumulate1_{config['workload']}_{config['value_storage']}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -230,7 +230,7 @@ def main():
     step_score_s = acc_ms / args.steps * 1e-3
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_accumulate (scoring pass)", "launch_ms": round(acc_ms_avg, 3),
+                "kernel": "k_accumulate1 (scoring pass)", "launch_ms": round(acc_ms_avg, 3),
                 "launches_per_step": launches_per_step,
                 "bytes_per_launch": bytes_per_launch, "batch": batch,
                 "postings_per_launch_union": union_post // launches_per_step,
