@@ -254,6 +254,37 @@ def test_long_query_in_the_call_does_not_change_results(sindi, small, batch):
                     pool_margin=_pool_margin(pid, psc, oracle.apply_mask(corpus, keep), long_q, 1e-5))
 
 
+def test_tile_runs_past_the_run_table(sindi):
+    """One workgroup sweeping a run of more than 64 tiles reloads its table of tile
+    constants mid-run; short queries (one segment of lists) and queries of over 64 terms
+    (several segments) give bit-identical results for every tile run, and match the
+    oracle's Alg. 4 on the same index.  (4,096 queries: the launch keeps a requested run
+    only while the grid still has 4,096 workgroups.)"""
+    vocab, window = 1_000, 1_000
+    corpus = synth.generate(20_000, vocab, nnz=("poisson", 30.0), seed=21)
+    short = synth.generate(4_092, vocab, nnz=("poisson", 20.0), seed=21, stream=1)
+    long_q = synth.generate(4, vocab, nnz=("poisson", 150.0), clip=(100, 200), seed=21, stream=2)
+    queries = synth.Csr(np.concatenate([short.indptr, short.indptr[-1] + long_q.indptr[1:]]),
+                        np.concatenate([short.indices, long_q.indices]),
+                        np.concatenate([short.values, long_q.values]), vocab)
+    idx = sindi.Index(corpus, alpha=0.5, window=window, tile=256)
+    assert idx.info()["n_tiles"] == 80
+    r_ids, r_sc = map(_np, idx.search(queries, 10, gamma=100, tile_run=1))
+    c_ids, c_sc = map(_np, idx.search_coarse(queries, 30, tile_run=1))
+    for run in (16, 65, 80, 1_000):
+        ids, sc = map(_np, idx.search(queries, 10, gamma=100, tile_run=run))
+        assert (ids == r_ids).all() and sc.tobytes() == r_sc.tobytes(), run
+        ids, sc = map(_np, idx.search_coarse(queries, 30, tile_run=run))
+        assert (ids == c_ids).all() and sc.tobytes() == c_sc.tobytes(), run
+    rows = list(range(0, 4_092, 256)) + [4_092, 4_093, 4_094, 4_095]
+    sub = queries.take_rows(rows)
+    keep = oracle.mass_prune(corpus, 0.5)
+    oidx = oracle.build_index(corpus, window, keep)
+    o_ids, o_sc, pid, psc = oracle.approx_search(oidx, corpus, sub, 1.0, 100, 10, want_pool=True)
+    check_same_topk(r_ids[rows], o_ids, o_sc, _tol_kth(corpus, sub, o_ids, o_sc, 1e-5),
+                    pool_margin=_pool_margin(pid, psc, oracle.apply_mask(corpus, keep), sub, 1e-5))
+
+
 def test_tile_size_and_query_mix_do_not_change_results(sindi, small):
     """Sec. 3.3.1: the window split only reorders the scan; here tiles are bit-invariant,
     and a query's result does not depend on which queries share its batch."""
