@@ -12,7 +12,7 @@
 //                  update): into the rerank pool, or sorted into the coarse
 //                  top-k (Alg. 2 alone)
 //   k_rerank       exact FP32 rerank of the pool from the unpruned vectors
-//                  (Alg. 4), one wave per pool entry
+//                  (Alg. 4), four pool entries per wave
 //   k_topk         top-k of the reranked pool (Alg. 4)
 //   k_score_*      delta(q, x) of listed pairs (Def. 2) and its gradient
 //
