@@ -1008,6 +1008,9 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                 // Loads are unconditional, so they leave back to back: lane l reads
                 // group g0 + l even past its chunk's end (at most 63 groups past the
                 // tile's last group: inside the arrays); those lanes add nothing.
+                // The wave issues them at raised priority, so waves about to load
+                // go ahead of waves adding into LDS.
+                __builtin_amdgcn_s_setprio(3);
 #pragma unroll
                 for (int i = 0; i < KU; ++i) {
                     const uint32_t ci = cs + (uint32_t)i;
@@ -1026,6 +1029,7 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     load_at(pd_t, gi * (uint32_t)sizeof(uint2), ids[i]);
                     load_at(pv_t, gi * (uint32_t)sizeof(Raw), raw[i]);
                 }
+                __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                 for (int i = 0; i < KU; ++i) {
                     if ((uint32_t)lane >= nl[i]) continue;
