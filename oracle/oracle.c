@@ -197,7 +197,9 @@ void or_pair_scores(const int64_t *dptr, const int32_t *didx, const float *dval,
 /* alpha-mass subvector (Defs. 5-6).  pi orders a row's entries by          */
 /* non-increasing |x| (ties: lower term id first); mass is the sum of |x|   */
 /* taken in that order; r is the smallest prefix length whose sum reaches   */
-/* alpha * mass; the first r entries of pi are kept.                        */
+/* alpha * mass; the first r entries of pi are kept.  A stored value of 0   */
+/* is no entry (Def. 1: a vector is the set of its non-zero entries), so it */
+/* is never kept, and a row of zeros keeps nothing.                         */
 typedef struct {
     double a;
     int32_t id;
@@ -211,14 +213,17 @@ static int cmp_mag(const void *x, const void *y)
     return (p->id > q->id) - (p->id < q->id);
 }
 
-static int64_t mass_prune_row(const int32_t *idx, const float *val, int64_t n, double alpha,
-                              mag_t *tmp, uint8_t *keep)
+static int64_t mass_prune_row(const int32_t *idx, const float *val, int64_t n_stored,
+                              double alpha, mag_t *tmp, uint8_t *keep)
 {
-    for (int64_t i = 0; i < n; ++i) {
-        tmp[i].a = fabs((double)val[i]);
-        tmp[i].id = idx[i];
-        tmp[i].pos = i;
+    int64_t n = 0;
+    for (int64_t i = 0; i < n_stored; ++i) {
         keep[i] = 0;
+        if (val[i] == 0.0f) continue;  /* not an entry of the vector (Def. 1) */
+        tmp[n].a = fabs((double)val[i]);
+        tmp[n].id = idx[i];
+        tmp[n].pos = i;
+        ++n;
     }
     if (n == 0) return 0;
     qsort(tmp, (size_t)n, sizeof(mag_t), cmp_mag);

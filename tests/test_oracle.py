@@ -59,6 +59,30 @@ def test_mass_prune_alpha_one_is_identity_and_empty_rows():
     assert (np.diff(csr.indptr) == 0).any()  # empty rows present and harmless
 
 
+def test_mass_prune_never_keeps_explicit_zeros():
+    """Def. 1: a sparse vector is the set of its non-zero entries, so a stored 0 is no entry
+    and no alpha keeps it; a row holding only zeros keeps nothing, and the zeros do not
+    change which non-zero entries a row keeps."""
+    csr = synth.Csr(np.array([0, 2, 5, 6], np.int64), np.array([1, 4, 0, 2, 3, 7], np.int32),
+                    np.array([0.0, 0.0, 0.5, 0.0, 0.5, 0.0], np.float32), 8)
+    for alpha in (0.1, 0.5, 1.0):
+        keep = oracle.mass_prune(csr, alpha)
+        assert keep[[0, 1, 3, 5]].tolist() == [0, 0, 0, 0], alpha
+    assert oracle.mass_prune(csr, 1.0)[[2, 4]].tolist() == [1, 1]
+    # alpha 0.5 of {0.5, 0.5}: the first (lower id) reaches half the mass alone
+    assert oracle.mass_prune(csr, 0.5)[[2, 4]].tolist() == [1, 0]
+    rng = np.random.default_rng(3)
+    c = synth.random_csr(rng, 300, 400, 30, signed=True)
+    z = c.values.copy()
+    z[::5] = 0.0
+    cz = synth.Csr(c.indptr, c.indices, z, c.n_cols)
+    stripped = oracle.apply_mask(cz, (z != 0).astype(np.uint8))
+    for alpha in (0.3, 0.8, 1.0):
+        keep = oracle.mass_prune(cz, alpha)
+        assert not keep[z == 0].any()
+        assert np.array_equal(keep[z != 0], oracle.mass_prune(stripped, alpha))
+
+
 @pytest.mark.parametrize("alpha", [0.3, 0.5, 0.7])
 def test_mass_prune_lognormal_closed_form(alpha):
     """For lognormal(0, s) entries the alpha-mass subvector keeps the entries above
