@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+CU_COUNT, CLOCK_HZ = 256, 2.4e9  # MI355X compute units, peak engine clock
 
 
 def log(msg):
@@ -56,6 +57,29 @@ def kernel_code_sha256(path):
     src = re.sub(r"//[^\n]*", " ", src)
     src = re.sub(r"\s+", " ", src).strip()
     return hashlib.sha256(src.encode()).hexdigest()
+
+
+def probe_lds(stream=None):
+    """LDS atomic-add rates of gfx950 (libsindi_probe.so): 32-bit integer adds with 64
+    consecutive words per instruction (no bank shared), with the 4-word lane stride of a
+    dense list read 4 postings per lane, and at pseudo-random words (the scatter of
+    postings), plus FP32 adds at random words.  Adds per second, over 4,096 workgroups of
+    512 threads (three per compute unit, as the scoring kernel's)."""
+    from paper_2509_08395_amd import _lib
+    lib = _lib.load_probe()
+    out = {}
+    for name, op, stride in (("int_conflict_free", 0, 1), ("int_stride4", 0, 4),
+                             ("int_random", 0, 0), ("f32_random", 1, 0)):
+        best = None
+        for _ in range(3):
+            ms, upd = _lib.probe_lds_add(lib, op, stride, 4096, 400 if op == 0 else 40)
+            rate = upd / (ms * 1e-3)
+            best = rate if best is None else max(best, rate)
+        out[name] = round(best, 1)
+    out["unit"] = "atomic adds/s (whole GPU)"
+    out["per_cu_clock"] = {k: round(v / (CU_COUNT * CLOCK_HZ), 3) for k, v in out.items()
+                           if isinstance(v, float)}
+    return out
 
 
 def measured_traffic(config):
@@ -113,7 +137,11 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--gamma", type=int, default=0)
-    ap.add_argument("--recall-queries", type=int, default=128)
+    ap.add_argument("--recall-queries", type=int, default=0,
+                    help="queries the live exact oracle scores (0: 16 to re-check the stored "
+                         "exact top-k of every query, or 1,000 without it)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the alpha / gamma / beta / storage sweep")
     ap.add_argument("--oracle-queries", type=int, default=7000)
     ap.add_argument("--no-oracle", action="store_true", help="skip recall and the CPU baseline")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
@@ -212,7 +240,7 @@ def main():
     qps = n_q * args.steps / elapsed
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {qps:.0f} QPS; kernels {prof}")
 
-    # roofline of the dominant kernel (scoring accumulate): algorithmic bytes per launch
+    # roofline of the dominant kernel (the scoring pass)
     term_len = idx.term_lengths()
     vbytes = {"f32": 4, "f16": 2, "bf16": 2}[dtype]
     bpp = 2 + vbytes
@@ -225,34 +253,59 @@ def main():
     n_launch, acc_ms = prof["accumulate_score"]
     launches_per_step = max(n_launch // args.steps, 1)
     acc_ms_avg = acc_ms / max(n_launch, 1)
+    launch_s = acc_ms_avg * 1e-3
     bytes_per_launch = algo_bytes // launches_per_step
-    achieved = bytes_per_launch / (acc_ms_avg * 1e-3) / 1e9 if acc_ms_avg > 0 else 0.0
-    step_score_s = acc_ms / args.steps * 1e-3
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_accumulate1 (scoring pass)", "launch_ms": round(acc_ms_avg, 3),
-                "launches_per_step": launches_per_step,
-                "bytes_per_launch": bytes_per_launch, "batch": batch,
-                "postings_per_launch_union": union_post // launches_per_step,
-                "useful_postings_per_s": round(query_post / step_score_s, 1) if acc_ms else 0}
+    post_per_launch = query_post // launches_per_step
+    config = {"workload": wl.name, "n_docs": corpus.n_rows, "vocab": wl.vocab,
+              "n_queries": n_q, "value_storage": dtype, "alpha": alpha,
+              "window": wl.window, "gamma": gamma, "k": k, "beta": wl.beta,
+              "batch": batch, "tile": info["tile_max"], "n_tiles": info["n_tiles"],
+              "n_postings": info["n_postings"]}
+    traffic = measured_traffic(config)
+    achieved = traffic / launch_s / 1e9 if traffic and launch_s > 0 else None
+    adds_per_s = post_per_launch / launch_s if launch_s > 0 else 0.0
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": traffic,
+        "achieved_is": "HBM bytes beyond L2 per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                       "copy-calibrated, profiles/) over the launch time by HIP events",
+        "kernel": "k_accumulate1 (scoring pass)", "launch_ms": round(acc_ms_avg, 3),
+        "launches_per_step": launches_per_step, "batch": batch,
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+        "algorithmic_GBs": round(bytes_per_launch / launch_s / 1e9, 1) if launch_s else None,
+        "algorithmic_note": "every query's lists once (2 B id + value bytes per posting, 8 B of "
+                            "list bounds per query term and tile); lists shared by queries "
+                            "scoring the same tile at once are served from L2",
+        "postings_per_launch": post_per_launch,
+        "useful_postings_per_s": round(adds_per_s, 1),
+        "paper_layout_8B_GBs": round(adds_per_s * 8 / 1e9, 1),
+    }
+    try:
+        probe = probe_lds()
+        roofline["lds"] = {
+            "posting_adds_per_s": round(adds_per_s, 1),
+            "conflict_free_adds_per_s": probe["int_conflict_free"],
+            "random_adds_per_s": probe["int_random"],
+            "frac": round(adds_per_s / probe["int_conflict_free"], 4),
+            "frac_of_random_rate": round(adds_per_s / probe["int_random"], 4),
+            "probe": probe}
+        log(f"LDS probe: {probe}")
+    except Exception as e:  # the probe library is measurement only
+        log(f"LDS probe unavailable: {e}")
 
     result = {
         "metric": "QPS at Recall@50>=99% vs exact oracle, 8.8M docs; % HBM roofline; p99 ms",
         "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl.name, "n_docs": corpus.n_rows, "vocab": wl.vocab,
-                   "n_queries": n_q, "value_storage": dtype, "alpha": alpha,
-                   "window": wl.window, "gamma": gamma, "k": k, "beta": wl.beta,
-                   "batch": batch, "tile": info["tile_max"], "n_tiles": info["n_tiles"],
-                   "n_postings": info["n_postings"]},
+        "config": config,
         "latency_ms_batch": round(ms_per_step, 3),
         "kernels_ms_per_step": {n: round(v[1] / args.steps, 3) for n, v in prof.items()},
         "build_s": round(build_s, 2),
         "build": build,
         "roofline": roofline,
     }
-    roofline["traffic"] = measured_traffic(result["config"])
 
     if args.serve_seconds > 0 and dtype == "f16" and wl.name == "splade-8.8m":
         result["serving"] = serving_leg(sindi, idx, args)
@@ -264,16 +317,29 @@ def main():
         result["differentiation"] = diff_leg(sindi)
 
     if not args.no_oracle:
-        import oracle  # CPU baseline and recall only
+        import oracle  # CPU baseline, recall and agreement only
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         gids = ids.cpu().numpy()
-        rsel = np.linspace(0, n_q - 1, min(args.recall_queries, n_q)).astype(np.int64)
+        stored = load_truth(wl, corpus, queries, k) if n_q == wl.n_queries else None
+        n_rec = args.recall_queries or (16 if stored is not None else 1000)
+        rsel = np.linspace(0, n_q - 1, min(n_rec, n_q)).astype(np.int64)
         qs = queries.take_rows(rsel)
         t = time.time()
         truth, _ = oracle.exact_topk(corpus, qs, k, threads=threads)
         exact_s = time.time() - t
-        rec = oracle.recall_at_k(gids[rsel], truth)
-        log(f"recall@{k} on {len(rsel)} queries: {rec:.5f} (exact oracle {exact_s:.1f}s)")
+        if stored is not None and not np.array_equal(stored[rsel], truth):
+            log("stored exact top-k disagrees with the oracle on the sampled queries: not used")
+            stored = None
+        if stored is not None:
+            tsel, truth_t = np.arange(n_q), stored
+            rec_note = (f"all {n_q} queries; exact FP64 top-{k} written by the oracle "
+                        f"(tests/golden, re-checked live on {len(rsel)} queries)")
+        else:
+            tsel, truth_t = rsel, truth
+            rec_note = f"{len(rsel)} of {n_q} queries, evenly spaced; exact FP64 oracle"
+        rec = oracle.recall_at_k(gids[tsel], truth_t)
+        log(f"recall@{k} on {len(tsel)} queries: {rec:.5f} (live exact oracle {exact_s:.1f}s "
+            f"for {len(rsel)})")
         osel = np.arange(min(args.oracle_queries, n_q))
         qo = queries.take_rows(osel)
         t = time.time()
@@ -283,16 +349,39 @@ def main():
         pruned = oracle.apply_mask(corpus, keep) if not args.no_precision and main_leg else None
         del keep
         t = time.time()
-        oracle.approx_search(oidx, corpus, qo, wl.beta, gamma, k, threads=threads)
+        o_ids, _ = oracle.approx_search(oidx, corpus, qo, wl.beta, gamma, k, threads=threads)
         oracle_s = time.time() - t
-        log(f"oracle Alg. 4 on {len(osel)} queries: {oracle_s:.1f}s (index {oracle_build_s:.1f}s)")
+        agree = oracle.recall_at_k(gids[osel], o_ids)
+        log(f"oracle Alg. 4 on {len(osel)} queries: {oracle_s:.1f}s (index {oracle_build_s:.1f}s), "
+            f"GPU agreement {agree:.5f}")
+        # single-thread figures, beside the paper's single-thread numbers
+        n1 = min(100, n_q)
+        t = time.time()
+        oracle.approx_search(oidx, corpus, queries.take_rows(np.arange(n1)), wl.beta, gamma, k,
+                             threads=1)
+        st_alg4 = n1 / (time.time() - t)
+        ne = min(8, n_q)
+        t = time.time()
+        oracle.exact_topk(corpus, queries.take_rows(np.arange(ne)), k, threads=1)
+        st_exact = ne / (time.time() - t)
+        del oidx
         result["recall_at_k"] = round(rec, 5)
-        result["recall_sample"] = f"{len(rsel)} of {n_q} queries, evenly spaced; exact FP64 oracle"
+        result["recall_sample"] = rec_note
+        result["alg4_agreement"] = round(agree, 5)
+        result["alg4_agreement_sample"] = (f"{len(osel)} of {n_q} queries: share of the CPU "
+                                           f"oracle's Alg. 4 top-{k} ids (FP64, same alpha, beta, "
+                                           "gamma) found in the GPU's")
         result["cpu_baseline"] = {
             "value": round(len(osel) / oracle_s, 3), "unit": "queries/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {len(osel)} of {n_q} queries, FP64 Alg. 4 (same alpha, gamma, k), "
-                      f"{oracle_s:.1f}s; exact FP64 top-{k}: {len(rsel) / exact_s:.3f} queries/s",
+            "sample": f"first {len(osel)} of {n_q} queries, FP64 Alg. 4 (same alpha, beta, gamma, "
+                      f"k), {oracle_s:.1f}s on {threads} threads",
+            "single_thread_alg4_qps": round(st_alg4, 3),
+            "single_thread_alg4_sample": f"first {n1} queries",
+            "exact_topk_qps": round(len(rsel) / exact_s, 3),
+            "exact_topk_sample": f"{len(rsel)} evenly spaced queries on {threads} threads",
+            "single_thread_exact_qps": round(st_exact, 4),
+            "single_thread_exact_sample": f"first {ne} queries",
             "cpu": _cpu_model()}
         if rec < 0.99:
             result["note"] = f"recall {rec:.4f} below 0.99"
@@ -302,10 +391,74 @@ def main():
                             "score_pass_ms": result["kernels_ms_per_step"]["accumulate_score"],
                             "recall_at_k": result["recall_at_k"], "bytes_per_posting": 4,
                             **coarse_error(idx, dqs, qs, pruned, k)}}
-            prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q,
+            prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, tsel, truth_t, n_q,
                                       dqs, qs, pruned))
             result["precision"] = prec
+        if not args.no_sweep and main_leg:
+            idx.close()  # room for the sweep's indexes
+            result["sweep"] = sweep_leg(sindi, corpus, dq, wl, k, tsel, truth_t, rec_note)
     print(json.dumps(result), flush=True)
+
+
+def load_truth(wl, corpus, queries, k):
+    """The exact top-k of every query of the workload as the oracle wrote it
+    (tests/golden/make_exact_truth.py), if present and written for this very input (sizes,
+    seed and a fingerprint of the generated arrays); else None."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_exact_truth as mt
+    path = mt.truth_path(wl.name, k)
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(str(z["meta"]))
+        ids = z["ids"].astype(np.int64)
+    want = {"n_docs": corpus.n_rows, "vocab": wl.vocab, "n_queries": queries.n_rows, "k": k,
+            "seed": wl.seed}
+    if any(meta.get(key) != v for key, v in want.items()):
+        return None
+    if meta.get("fingerprint") != mt.fingerprint(corpus, queries):
+        return None
+    return ids
+
+
+def sweep_leg(sindi, corpus, dq, wl, k, tsel, truth, rec_note, steps=3):
+    """The parameters of Sec. 5.3 and Sec. 4.1 around the configuration point: alpha in {0.2,
+    0.3, 0.4, 0.5}, gamma in {200, 500}, beta in {0.8, 1.0}, FP16 and FP32 posting values
+    (each index built on the device), each searched over the whole query set: QPS and
+    Recall@k, then per storage type the fastest point with Recall@k >= 0.99."""
+    import torch
+    import oracle
+    n_q = dq.n_rows
+    ids = torch.empty((n_q, k), dtype=torch.int64, device="cuda")
+    sc = torch.empty((n_q, k), dtype=torch.float32, device="cuda")
+    rows = []
+    for dt in ("f16", "f32"):
+        for a in (0.2, 0.3, 0.4, 0.5):
+            idx = sindi.Index(corpus, alpha=a, window=wl.window, value_dtype=dt, gpu_build=True)
+            for g in (200, 500):
+                for b in (0.8, 1.0):
+                    idx.search(dq, k, beta=b, gamma=g, out=(ids, sc))
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(steps):
+                        idx.search(dq, k, beta=b, gamma=g, out=(ids, sc))
+                    torch.cuda.synchronize()
+                    el = time.perf_counter() - t0
+                    rec = oracle.recall_at_k(ids.cpu().numpy()[tsel], truth)
+                    rows.append({"value_storage": dt, "alpha": a, "gamma": g, "beta": b,
+                                 "qps": round(n_q * steps / el, 1), "recall_at_k": round(rec, 5)})
+                    log(f"sweep {rows[-1]}")
+            idx.close()
+            del idx
+    best = {}
+    for dt in ("f16", "f32"):
+        ok = [r for r in rows if r["value_storage"] == dt and r["recall_at_k"] >= 0.99]
+        best[dt] = max(ok, key=lambda r: r["qps"]) if ok else None
+    cfg = {dt: next(r for r in rows if r["value_storage"] == dt and r["alpha"] == 0.5
+                    and r["gamma"] == 500 and r["beta"] == 1.0) for dt in ("f16", "f32")}
+    return {"grid": "alpha {0.2,0.3,0.4,0.5} x gamma {200,500} x beta {0.8,1.0} x {f16,f32}",
+            "recall_sample": rec_note, "steps": steps, "config_point": cfg,
+            "best_at_recall_0.99": best, "rows": rows}
 
 
 def coarse_error(idx, dqs, qs, pruned, k):
@@ -330,7 +483,7 @@ def precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q, dqs,
     import oracle
     out = {}
     for dt in ("f32", "bf16"):
-        idx = sindi.Index(corpus, alpha=alpha, window=wl.window, value_dtype=dt)
+        idx = sindi.Index(corpus, alpha=alpha, window=wl.window, value_dtype=dt, gpu_build=True)
         ids = torch.empty((n_q, k), dtype=torch.int64, device="cuda")
         sc = torch.empty((n_q, k), dtype=torch.float32, device="cuda")
         idx.search(dq, k, gamma=gamma, out=(ids, sc))
@@ -404,6 +557,19 @@ def serving_leg(sindi, idx, args):
     rates = ([float(x) for x in args.serve_rates.split(",")] if args.serve_rates
              else list(wl.extra["rates"]))
     out = []
+    # the GPU's rate on this query mix with no request loop: one search call over 7,000
+    # serving-shaped queries (k = 100), the ceiling the loop's batches approach
+    import torch
+    qb = sindi.DeviceCsr.from_host(wl.queries(7_000, row0=1 << 40))
+    idx.search(qb, 100, gamma=wl.gamma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        idx.search(qb, 100, gamma=wl.gamma)
+    torch.cuda.synchronize()
+    batch_qps = 3 * 7_000 / (time.perf_counter() - t0)
+    log(f"serving mix, one call of 7,000 queries: {batch_qps:.0f} QPS")
+    del qb
     row0 = 0
     with sindi.Server(idx, max_inflight=2, max_batch=512, k_max=100, gamma=wl.gamma) as srv:
         for i, rate in enumerate(rates):
@@ -428,6 +594,7 @@ def serving_leg(sindi, idx, args):
             log(f"serving {rec}")
             out.append(rec)
     return {"workload": "serving", "query_nnz": "uniform 5..200", "k": "uniform {10, 50, 100}",
+            "batch_call_qps": round(batch_qps, 1),
             "gamma": wl.gamma, "seconds_per_rate": args.serve_seconds, "max_inflight": 2,
             "max_batch": 512, "rates": out}
 
@@ -471,13 +638,26 @@ def ablation(args, n_docs=1_000_000, n_queries=1_000, gammas=(10, 30, 100), k=10
 
 
 def _cpu_model():
+    """The host CPU as /proc/cpuinfo names it (model name, family/model/stepping, clock), with
+    the logical CPUs this process may run on."""
+    fields = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                key, val = (x.strip() for x in line.split(":", 1))
+                if key in ("model name", "cpu family", "model", "stepping", "cpu MHz",
+                           "vendor_id") and key not in fields:
+                    fields[key] = val
     except OSError:
         pass
-    return "unknown"
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    name = fields.get("model name", "unknown")
+    return (f"{name} (vendor {fields.get('vendor_id', '?')}, family {fields.get('cpu family', '?')} "
+            f"model {fields.get('model', '?')} stepping {fields.get('stepping', '?')}, "
+            f"{fields.get('cpu MHz', '?')} MHz; {usable} usable of {os.cpu_count()} logical CPUs)")
 
 
 if __name__ == "__main__":

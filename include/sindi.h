@@ -190,12 +190,23 @@ sindi_status sindi_search_coarse(const sindi_index *idx, const sindi_csr *querie
 
 /*
  * Scores of listed candidates: out_scores[b*n_cand + c] = delta(q_b, x_{cand})
- * (Def. 2) in FP32 from the unpruned corpus; cand id -1 gives 0.
- *   queries  CSR (device memory), cand_ids device int64 [n_rows * n_cand]
+ * (Def. 2) in FP32 over the unpruned corpus rows; cand id -1 (or any id
+ * outside [0, n_docs)) gives 0.
+ *   queries     CSR (device memory) over the index's vocabulary
+ *   cand_ids    device int64 [n_rows * n_cand]
+ *   doc_values  device float [nnz]: document values aligned with the corpus
+ *               values given to sindi_build (same rows and term ids, new
+ *               values, e.g. a document encoder's current output), or NULL
+ *               to score the values the index copied at build time.  The
+ *               inverted lists that sindi_search reads are not affected.
+ *   out_scores  device float [n_rows * n_cand]
+ * Enqueued on the stream after the queries are validated (which waits for
+ * the stream); the caller keeps every buffer alive until the stream reaches
+ * the call.
  */
 sindi_status sindi_score_forward(const sindi_index *idx, const sindi_csr *queries,
-                                 const int64_t *cand_ids, int32_t n_cand, float *out_scores,
-                                 void *stream);
+                                 const int64_t *cand_ids, int32_t n_cand,
+                                 const float *doc_values, float *out_scores, void *stream);
 
 /*
  * Backward of sindi_score_forward.  The score is bilinear in the values, so
@@ -203,24 +214,33 @@ sindi_status sindi_score_forward(const sindi_index *idx, const sindi_csr *querie
  *   grad_query_values[e] += sum_c G[b,c] * x_c[t]     (entry e = (b, t))
  *   grad_doc_values[e']  += sum_b G[b,c] * q_b[t]     (entry e' = (c, t))
  * over common dimensions t only; entries outside every intersection are
- * untouched.  grad_query_values is aligned with queries->values (device,
- * [queries->nnz]); grad_doc_values with the corpus values given to
- * sindi_build (device, [nnz]).  Either may be NULL.  Accumulates (+=).
- * Candidate ids -1 are skipped.
+ * untouched.  x is doc_values when given (as for sindi_score_forward), else
+ * the index's copy.  grad_query_values is aligned with queries->values
+ * (device, [queries->nnz]); grad_doc_values with the corpus values given to
+ * sindi_build (device, [nnz]).  Either may be NULL.  Accumulates (+=); the
+ * document side adds with atomics, so the order of its FP32 additions is
+ * not fixed.  Candidate ids -1 are skipped.
  */
 sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queries,
                                   const int64_t *cand_ids, int32_t n_cand,
-                                  const float *grad_scores, float *grad_query_values,
-                                  float *grad_doc_values, void *stream);
+                                  const float *doc_values, const float *grad_scores,
+                                  float *grad_query_values, float *grad_doc_values,
+                                  void *stream);
 
 /*
  * ---------------------------------------------------------------- serving
  * Continuous batching over one index (the paper measures single queries;
  * this is the request loop around Alg. 4).  Requests are queued as they
- * arrive; a dispatcher thread owned by the server takes every queued request
- * (up to max_batch) into a batch as soon as one of max_inflight batch slots
- * is free, and runs the whole search of that batch asynchronously on the
- * slot's own HIP stream, so batches overlap on the device.  A batch runs with
+ * arrive; a dispatcher thread owned by the server admits queued requests into
+ * a batch as soon as one of max_inflight batch slots is free and the
+ * candidate memory the batch needs (sampled maxima, candidate lists, rerank
+ * pools: about 330 KB per query at the defaults) fits in the largest free
+ * block of one device arena of workspace_bytes shared by every batch in
+ * flight: as many requests as are queued, up to max_batch and up to what fits.
+ * It runs the whole search of that batch asynchronously on the slot's own HIP
+ * stream, so batches overlap on the device.  A query whose sampled candidate
+ * threshold missed is re-run on the same stream (a threshold over every tile,
+ * then none) without holding up the dispatcher.  A batch runs with
  * the largest k any of its requests asks for; every request gets the prefix
  * of its own k.  Scoring is deterministic and independent of which other
  * queries share a batch, so a request's result equals what sindi_search
@@ -234,7 +254,8 @@ typedef struct {
     int32_t k_max;            /* largest k of a request, <= gamma; 0 -> 100                  */
     int32_t max_query_nnz;    /* longest query row accepted; 0 -> 512, at most 4096          */
     int64_t max_queue;        /* queued requests before submit returns SINDI_E_BUSY; 0 -> 2^20 */
-    int64_t workspace_bytes;  /* candidate buffer bytes per slot; 0 -> 1 GiB                 */
+    int64_t workspace_bytes;  /* candidate memory shared by the batches in flight; 0 -> 2 GiB
+                                 (raised to hold at least one query)                         */
     sindi_search_params search;  /* beta, gamma, cand_cap, sample_tiles, tile_run as for
                                     sindi_search; gamma 0 -> max(k_max, 500)                 */
 } sindi_server_params;
@@ -243,6 +264,8 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, batches, retried, largest_batch;
     double busy_ms;           /* wall time with at least one batch on the device          */
+    int64_t memory_waits;     /* times queued requests waited for candidate memory        */
+    int64_t arena_peak_bytes; /* most candidate memory held by the batches in flight      */
 } sindi_server_stats;
 
 typedef struct sindi_server sindi_server;

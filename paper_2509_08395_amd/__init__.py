@@ -96,6 +96,22 @@ class DeviceCsr:
                              self.indices.data_ptr(), self.values.data_ptr(), 1, 0)
 
 
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _vector_arg(t, n, name):
+    """None, or a contiguous float32 CUDA tensor of n elements (the kernels write or read
+    exactly n)."""
+    import torch
+    if t is None:
+        return
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32
+            or not t.is_contiguous() or t.numel() != n):
+        raise SindiError(_lib.SINDI_E_INVALID,
+                         f"{name} must be a contiguous CUDA float32 tensor of {n} elements")
+
+
 def _query_struct(queries):
     if isinstance(queries, DeviceCsr):
         return queries.struct(), queries
@@ -123,6 +139,7 @@ class Index:
                                    ctypes.byref(handle)))
         self._h = handle
         self.n_cols = h.n_cols
+        self.nnz = h.nnz
         self.value_dtype = value_dtype
 
     def close(self):
@@ -221,28 +238,47 @@ class Index:
         return self._run(_lib.load().sindi_search_coarse, queries, k, beta, 0, batch, cand_cap,
                          sample_tiles, stream, out, tile_run)
 
-    def score(self, queries: DeviceCsr, cand, stream=None):
-        """delta(q_b, x_c) for cand [n_q, n_cand] (int64 CUDA) -> float32 [n_q, n_cand]."""
+    def _score_args(self, queries, cand, doc_values):
+        """Checks the shapes the score kernels index by (they cannot see buffer sizes)."""
         import torch
-        cand = cand.contiguous()
+        if not isinstance(queries, DeviceCsr):
+            raise SindiError(_lib.SINDI_E_INVALID, "score: queries must be a DeviceCsr")
+        if (not isinstance(cand, torch.Tensor) or not cand.is_cuda or cand.dtype != torch.int64
+                or cand.dim() != 2 or cand.shape[0] != queries.n_rows):
+            raise SindiError(_lib.SINDI_E_INVALID,
+                             f"score: cand must be a CUDA int64 tensor [{queries.n_rows}, n_cand]")
+        _vector_arg(doc_values, self.nnz, "doc_values")
+        return queries.struct(), cand.contiguous()
+
+    def score(self, queries: DeviceCsr, cand, doc_values=None, stream=None):
+        """delta(q_b, x_c) for cand [n_q, n_cand] (int64 CUDA) -> float32 [n_q, n_cand].
+
+        doc_values (float32 CUDA [nnz], aligned with the corpus values the index was built
+        from): the document values to score; None scores the index's build-time copy."""
+        import torch
+        qs, cand = self._score_args(queries, cand, doc_values)
         out = torch.empty(cand.shape, dtype=torch.float32, device="cuda")
-        qs = queries.struct()
         _lib.check(_lib.load().sindi_score_forward(self._h, ctypes.byref(qs),
                                                    ctypes.c_void_p(cand.data_ptr()),
-                                                   int(cand.shape[1]),
+                                                   int(cand.shape[1]), _ptr(doc_values),
                                                    ctypes.c_void_p(out.data_ptr()),
                                                    _stream(stream)))
         return out
 
     def score_backward(self, queries: DeviceCsr, cand, grad, grad_query=None, grad_doc=None,
-                       stream=None):
-        cand = cand.contiguous()
+                       doc_values=None, stream=None):
+        """Adds dL/dq into grad_query [queries.nnz] and dL/dx into grad_doc [nnz] (float32
+        CUDA, either may be None) for grad = dL/dscore [n_q, n_cand]."""
+        qs, cand = self._score_args(queries, cand, doc_values)
+        if (not hasattr(grad, "is_cuda") or not grad.is_cuda or tuple(grad.shape) != tuple(cand.shape)):
+            raise SindiError(_lib.SINDI_E_INVALID, "score_backward: grad must be a CUDA tensor "
+                             f"shaped like cand {tuple(cand.shape)}")
         grad = grad.contiguous().float()
-        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
-        qs = queries.struct()
-        _lib.check(_lib.load().sindi_score_backward(self._h, ctypes.byref(qs), ptr(cand),
-                                                    int(cand.shape[1]), ptr(grad),
-                                                    ptr(grad_query), ptr(grad_doc),
+        _vector_arg(grad_query, queries.nnz, "grad_query")
+        _vector_arg(grad_doc, self.nnz, "grad_doc")
+        _lib.check(_lib.load().sindi_score_backward(self._h, ctypes.byref(qs), _ptr(cand),
+                                                    int(cand.shape[1]), _ptr(doc_values),
+                                                    _ptr(grad), _ptr(grad_query), _ptr(grad_doc),
                                                     _stream(stream)))
 
 
@@ -338,26 +374,27 @@ def _make_score_fn():
     class SindiScore(torch.autograd.Function):
         """s[b, c] = delta(q_b, x_{cand[b, c]}) with hand-written HIP forward and backward.
 
-        Inputs: query values (requires_grad), document values of the corpus the index
-        was built from (requires_grad; the index holds its own copy of these values,
-        so they must not change after the build), the index, the query CSR structure
-        (indptr, indices) and candidate ids [n_q, n_cand].
+        Inputs: query values (requires_grad), document values (requires_grad; float32
+        CUDA [nnz], aligned entry for entry with the corpus the index was built from: same
+        rows and term ids, values free to change, e.g. as a document encoder trains), the
+        index, the query CSR structure (indptr, indices) and candidate ids [n_q, n_cand].
+        The scores and both gradients use the doc_values passed, not the index's
+        build-time copy; only the candidates a search returns depend on that copy.
         """
 
         @staticmethod
         def forward(ctx, q_values, doc_values, index, q_indptr, q_indices, cand):
             qs = DeviceCsr(q_indptr, q_indices, q_values.detach().contiguous(), index.n_cols)
-            ctx.index, ctx.qs, ctx.cand = index, qs, cand
-            ctx.doc_shape = doc_values.shape
+            xv = doc_values.detach().contiguous()
+            ctx.index, ctx.qs, ctx.cand, ctx.xv = index, qs, cand, xv
             ctx.needs = (ctx.needs_input_grad[0], ctx.needs_input_grad[1])
-            return index.score(qs, cand)
+            return index.score(qs, cand, doc_values=xv)
 
         @staticmethod
         def backward(ctx, grad):
             gq = torch.zeros_like(ctx.qs.values) if ctx.needs[0] else None
-            gx = (torch.zeros(ctx.doc_shape, dtype=torch.float32, device="cuda")
-                  if ctx.needs[1] else None)
-            ctx.index.score_backward(ctx.qs, ctx.cand, grad, gq, gx)
+            gx = torch.zeros_like(ctx.xv) if ctx.needs[1] else None
+            ctx.index.score_backward(ctx.qs, ctx.cand, grad, gq, gx, doc_values=ctx.xv)
             return gq, gx, None, None, None, None
 
     return SindiScore

@@ -57,7 +57,8 @@ class SindiServerParams(ctypes.Structure):
 class SindiServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("retried", ctypes.c_int64),
-                ("largest_batch", ctypes.c_int64), ("busy_ms", ctypes.c_double)]
+                ("largest_batch", ctypes.c_int64), ("busy_ms", ctypes.c_double),
+                ("memory_waits", ctypes.c_int64), ("arena_peak_bytes", ctypes.c_int64)]
 
 
 class SindiProfile(ctypes.Structure):
@@ -105,8 +106,8 @@ def load():
     lib.sindi_index_export.argtypes = [P, P, P, P, P, P]
     for f in (lib.sindi_search, lib.sindi_search_coarse):
         f.argtypes = [P, ctypes.POINTER(SindiCsr), I32, ctypes.POINTER(SindiSearchParams), P, P, P]
-    lib.sindi_score_forward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P]
-    lib.sindi_score_backward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P, P, P]
+    lib.sindi_score_forward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P, P]
+    lib.sindi_score_backward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P, P, P, P]
     for f in (lib.sindi_build, lib.sindi_index_get_info, lib.sindi_index_export,
               lib.sindi_search, lib.sindi_search_coarse, lib.sindi_score_forward,
               lib.sindi_score_backward):
@@ -131,6 +132,37 @@ def load():
     lib.sindi_version.argtypes = []
     _lib = lib
     return lib
+
+
+PROBE_PATH = os.path.join(PKG, "libsindi_probe.so")
+PROBE_EXPORTS = ("sindi_probe_lds_add",)
+_probe = None
+
+
+def load_probe():
+    """libsindi_probe.so (include/sindi_probe.h): the LDS microbenchmark bench.py reports."""
+    global _probe
+    if _probe is None:
+        load()  # torch's HIP runtime first, as for the search library
+        if not os.path.exists(PROBE_PATH):
+            raise ImportError(f"{PROBE_PATH} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(PROBE_PATH)
+        lib.sindi_probe_lds_add.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double)]
+        lib.sindi_probe_lds_add.restype = ctypes.c_int
+        _probe = lib
+    return _probe
+
+
+def probe_lds_add(lib, op, stride, n_workgroups, iters, stream=None):
+    """(milliseconds, atomic adds) of one probe launch; raises on a HIP error."""
+    ms, upd = ctypes.c_double(), ctypes.c_double()
+    rc = lib.sindi_probe_lds_add(int(op), int(stride), int(n_workgroups), int(iters), stream,
+                                 ctypes.byref(ms), ctypes.byref(upd))
+    if rc != 0:
+        raise SindiError(SINDI_E_HIP, f"sindi_probe_lds_add: hipError {rc}")
+    return ms.value, upd.value
 
 
 def check(code):

@@ -632,6 +632,7 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
 sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
                        const sindi_search_params &p, bool rerank, const char *fn, Plan &pl)
 {
+    (void)nq;
     pl = Plan{};
     pl.rerank = rerank;
     pl.k = k;
@@ -666,132 +667,225 @@ sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
             sampled += td[t + 1] - td[t];
         }
         const double f = (double)sampled / (double)ix->n_docs;
-        pl.n_max = (int64_t)pl.n_sample * kAccThreads;
-        pl.rank = std::min<int64_t>(pl.n_max, (int64_t)std::ceil(2.0 * pl.need * f) + 8);
+        pl.rank = std::min<int64_t>((int64_t)pl.n_sample * kAccThreads,
+                                    (int64_t)std::ceil(2.0 * pl.need * f) + 8);
     }
-    pl.group = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(kCandBudget / plan_query_bytes(pl))));
-    return SINDI_OK;
-}
-
-sindi_status reserve_workspace(Workspace &ws, const Plan &pl, int64_t nq, int64_t nnz)
-{
-    HIP_TRY(ws.ct.ensure((size_t)nnz * 4 + 4));
-    HIP_TRY(ws.cw.ensure((size_t)nnz * 4 + 4));
-    HIP_TRY(ws.cn.ensure((size_t)nq * 4 + 4));
-    HIP_TRY(ws.qinv.ensure((size_t)nq * 4 + 4));
-    HIP_TRY(ws.sabs.ensure(pl.beta < 1.0 ? (size_t)nnz * 8 + 8 : 8));
-    HIP_TRY(ws.err.ensure(8));
-    HIP_TRY(ws.status.ensure((size_t)nq * 4 + 4));
-    const int64_t g = std::min<int64_t>(pl.group, std::max<int64_t>(nq, 1));
-    HIP_TRY(ws.cand.ensure((size_t)g * pl.cap * 8));
-    HIP_TRY(ws.count.ensure((size_t)g * 4));
-    HIP_TRY(ws.theta.ensure((size_t)g * 4));
-    HIP_TRY(ws.slot_q.ensure((size_t)g * 4));
-    if (!pl.keep_all) HIP_TRY(ws.maxima.ensure((size_t)g * pl.n_max * 4));
-    if (pl.rerank) HIP_TRY(ws.pool.ensure((size_t)g * pl.need * 8));
-    return SINDI_OK;
-}
-
-sindi_status enqueue_prep(const sindi_index *ix, Workspace &ws, const Plan &pl,
-                          const DevQueries &dq, hipStream_t s)
-{
-    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 2, 0u, s));
-    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
-    HIP_TRY(timed(kProfPrep, s, [&] {
-        return launch_query_prep(dq, ix->n_cols, pl.beta, dc, ix->term_max.as<float>(),
-                                 ws.sabs.as<double>(), ws.err.as<int32_t>(), s);
-    }));
-    return SINDI_OK;
-}
-
-sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl,
-                            const DevQueries &dq, int64_t *out_ids, float *out_scores,
-                            hipStream_t s)
-{
-    const int64_t nq = dq.n_rows;
-    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
-    if (ix->n_docs == 0) {
-        HIP_TRY(launch_fill_f32(out_scores, nq * pl.k, -INFINITY, s));
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(out_ids), 2 * nq * pl.k, 0xFFFFFFFFu, s));
-        HIP_TRY(launch_fill_u32(ws.status.as<uint32_t>(), nq, (uint32_t)kSlotOk, s));
-        return SINDI_OK;
-    }
-    const DevIndex dix = ix->dev();
-    for (int64_t g0 = 0; g0 < nq; g0 += pl.group) {
-        const int32_t ns = (int32_t)std::min<int64_t>(pl.group, nq - g0);
-        HIP_TRY(launch_iota(ws.slot_q.as<int32_t>(), ns, (int32_t)g0, s));
-        if (pl.keep_all) {
-            HIP_TRY(launch_fill_f32(ws.theta.as<float>(), ns, -INFINITY, s));
-        } else {
-            HIP_TRY(timed(kProfSample, s, [&] {
-                return launch_accumulate(dix, dq, dc, pl.batch, true, ws.slot_q.as<int32_t>(), ns,
-                                         pl.n_sample, ws.maxima.as<float>(), nullptr, nullptr,
-                                         nullptr, 0, pl.tile_run, pl.max_qnnz, s);
-            }));
-            HIP_TRY(timed(kProfTheta, s, [&] {
-                return launch_theta(ws.maxima.as<float>(), pl.n_max, pl.rank, ns,
-                                    ws.theta.as<float>(), s);
-            }));
-        }
-        HIP_TRY(launch_fill_u32(ws.count.as<uint32_t>(), ns, 0u, s));
-        HIP_TRY(timed(kProfScore, s, [&] {
-            return launch_accumulate(dix, dq, dc, pl.batch, false, ws.slot_q.as<int32_t>(), ns, 0,
-                                     nullptr, ws.theta.as<float>(), ws.count.as<uint32_t>(),
-                                     ws.cand.as<uint64_t>(), pl.cap, pl.tile_run, pl.max_qnnz, s);
-        }));
-        HIP_TRY(timed(kProfFinal, s, [&] {
-            return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
-                                   ws.cand.as<uint64_t>(), ws.theta.as<float>(), pl.cap, pl.need,
-                                   pl.k, pl.rerank, pl.max_qnnz, ws.pool.as<uint64_t>(), out_ids,
-                                   out_scores, ws.status.as<int32_t>(), s);
-        }));
-    }
-    return SINDI_OK;
-}
-
-sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
-                           const DevQueries &dq, const std::vector<int32_t> &rows,
-                           int64_t *out_ids, float *out_scores, hipStream_t s, const char *fn)
-{
-    if (rows.empty()) return SINDI_OK;
-    const DevIndex dix = ix->dev();
-    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
-    // threshold missed gamma candidates or overflowed: keep every document
-    const int64_t cap_all = ix->n_docs;
-    const int64_t g_all = std::max<int64_t>(1, (int64_t)(kCandBudget / ((size_t)cap_all * 8)));
-    const int64_t gsz = std::min<int64_t>(g_all, (int64_t)rows.size());
-    HIP_TRY(ws.cand.ensure((size_t)gsz * cap_all * 8));
-    HIP_TRY(ws.count.ensure((size_t)gsz * 4));
-    HIP_TRY(ws.theta.ensure((size_t)gsz * 4));
-    HIP_TRY(ws.slot_q.ensure((size_t)gsz * 4));
-    if (pl.rerank) HIP_TRY(ws.pool.ensure((size_t)gsz * pl.need * 8));
-    for (size_t g0 = 0; g0 < rows.size(); g0 += (size_t)gsz) {
-        const int32_t ns = (int32_t)std::min<size_t>((size_t)gsz, rows.size() - g0);
-        HIP_TRY(hipMemcpyAsync(ws.slot_q.p, rows.data() + g0, (size_t)ns * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_fill_f32(ws.theta.as<float>(), ns, -INFINITY, s));
-        HIP_TRY(launch_fill_u32(ws.count.as<uint32_t>(), ns, 0u, s));
-        HIP_TRY(timed(kProfScore, s, [&] {
-            return launch_accumulate(dix, dq, dc, 1, false, ws.slot_q.as<int32_t>(), ns, 0, nullptr,
-                                     ws.theta.as<float>(), ws.count.as<uint32_t>(),
-                                     ws.cand.as<uint64_t>(), cap_all, pl.tile_run, pl.max_qnnz, s);
-        }));
-        HIP_TRY(timed(kProfFinal, s, [&] {
-            return launch_finalize(dix, dq, ws.slot_q.as<int32_t>(), ns, ws.count.as<uint32_t>(),
-                                   ws.cand.as<uint64_t>(), nullptr, cap_all, pl.need, pl.k,
-                                   pl.rerank, pl.max_qnnz, ws.pool.as<uint64_t>(), out_ids,
-                                   out_scores, ws.status.as<int32_t>(), s);
-        }));
-        HIP_TRY(hipStreamSynchronize(s));  // rows[] is pageable host memory
-    }
-    std::vector<int32_t> status((size_t)dq.n_rows);
-    HIP_TRY(hipMemcpyAsync(status.data(), ws.status.p, (size_t)dq.n_rows * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int32_t q : rows)
-        if (status[q] != kSlotOk) return fail(SINDI_E_INTERNAL, "%s: query %d unresolved", fn, q);
     return SINDI_OK;
 }
 
 namespace {
+inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t scratch_row_bytes(const Plan &pl, int64_t nq, int64_t nnz)
+{
+    const size_t e = (size_t)std::max<int64_t>(nnz, 1), q = (size_t)std::max<int64_t>(nq, 1);
+    return 2 * align256(e * 4) + align256(pl.beta < 1.0 ? e * 8 : 8) + 5 * align256(q * 4) +
+           2 * align256(8);
+}
+
+Scratch carve_rows(unsigned char *p, const Plan &pl, int64_t nq, int64_t nnz)
+{
+    const size_t e = (size_t)std::max<int64_t>(nnz, 1), q = (size_t)std::max<int64_t>(nq, 1);
+    Scratch sc;
+    auto take = [&](size_t bytes) {
+        unsigned char *r = p;
+        p += align256(bytes);
+        return r;
+    };
+    sc.ct = reinterpret_cast<int32_t *>(take(e * 4));
+    sc.cw = reinterpret_cast<float *>(take(e * 4));
+    sc.sabs = reinterpret_cast<double *>(take(pl.beta < 1.0 ? e * 8 : 8));
+    sc.cn = reinterpret_cast<int32_t *>(take(q * 4));
+    sc.qinv = reinterpret_cast<float *>(take(q * 4));
+    sc.status = reinterpret_cast<int32_t *>(take(q * 4));
+    sc.rows = reinterpret_cast<int32_t *>(take(q * 4));
+    sc.rows2 = reinterpret_cast<int32_t *>(take(q * 4));
+    sc.err = reinterpret_cast<int32_t *>(take(8));
+    sc.n_rows = reinterpret_cast<uint32_t *>(take(8));
+    return sc;
+}
+
+PassShape pass_shape(const sindi_index *ix, const Plan &pl, PassKind kind)
+{
+    PassShape sh;
+    if (kind == kPassKeepAll || (kind == kPassSampled && pl.keep_all)) {
+        sh.keep_all = true;
+        sh.cap = std::max<int64_t>(ix->n_docs, 1);
+        return sh;
+    }
+    sh.cap = pl.cap;
+    if (kind == kPassSampled) {
+        sh.n_sample = pl.n_sample;
+        sh.rank = pl.rank;
+    } else {
+        sh.n_sample = (int32_t)ix->n_tiles;
+        sh.rank = pl.need;
+    }
+    sh.n_max = (int64_t)sh.n_sample * kAccThreads;
+    sh.rank = std::min<int64_t>(sh.rank, sh.n_max);
+    return sh;
+}
+
+size_t pass_bytes(const PassShape &sh, const Plan &pl, int64_t g)
+{
+    const size_t n = (size_t)g;
+    return 3 * align256(n * 4) + align256(n * (size_t)sh.n_max * 4) + align256(n * (size_t)sh.cap * 8) +
+           (pl.rerank ? align256(n * (size_t)pl.need * 8) : 0);
+}
+
+int64_t pass_group(const PassShape &sh, const Plan &pl, size_t bytes)
+{
+    // pass_bytes(g) >= g * per (alignment only adds, at most 255 bytes per array), so
+    // bytes / per bounds g from above and few steps down reach the largest fit
+    const size_t per = 12 + (size_t)sh.n_max * 4 + (size_t)sh.cap * 8 + (pl.rerank ? (size_t)pl.need * 8 : 0);
+    int64_t g = (int64_t)(bytes / per);
+    while (g > 0 && pass_bytes(sh, pl, g) > bytes) --g;
+    return g;
+}
+
+sindi_status enqueue_prep(const sindi_index *ix, const Scratch &sc, const Plan &pl,
+                          const DevQueries &dq, hipStream_t s)
+{
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(sc.err), 2, 0u, s));
+    DevCoarse dc{sc.ct, sc.cw, sc.cn, sc.qinv};
+    HIP_TRY(timed(kProfPrep, s, [&] {
+        return launch_query_prep(dq, ix->n_cols, pl.beta, dc, ix->term_max.as<float>(), sc.sabs,
+                                 sc.err, s);
+    }));
+    return SINDI_OK;
+}
+
+sindi_status enqueue_passes(const sindi_index *ix, const Scratch &sc, const Plan &pl,
+                            PassKind kind, const DevQueries &dq, const int32_t *rows, int64_t n,
+                            int64_t *out_ids, float *out_scores, hipStream_t s)
+{
+    if (n <= 0) return SINDI_OK;
+    if (ix->n_docs == 0) {  // every query row: k paddings
+        if (rows) return fail(SINDI_E_INTERNAL, "search: a retry over an empty index");
+        HIP_TRY(launch_fill_f32(out_scores, n * pl.k, -INFINITY, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(out_ids), 2 * n * pl.k, 0xFFFFFFFFu, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(sc.status), n, (uint32_t)kSlotOk, s));
+        return SINDI_OK;
+    }
+    const PassShape sh = pass_shape(ix, pl, kind);
+    const int64_t g = std::min<int64_t>(pass_group(sh, pl, sc.arena_bytes), n);
+    if (g < 1)
+        return fail(SINDI_E_INTERNAL, "search: scratch of %zu bytes holds no query of the pass",
+                    sc.arena_bytes);
+    unsigned char *p = sc.arena;
+    auto take = [&](size_t bytes) {
+        unsigned char *r = p;
+        p += align256(bytes);
+        return r;
+    };
+    int32_t *slot_q = reinterpret_cast<int32_t *>(take((size_t)g * 4));
+    uint32_t *count = reinterpret_cast<uint32_t *>(take((size_t)g * 4));
+    float *theta = reinterpret_cast<float *>(take((size_t)g * 4));
+    float *maxima = reinterpret_cast<float *>(take((size_t)g * sh.n_max * 4));
+    uint64_t *cand = reinterpret_cast<uint64_t *>(take((size_t)g * sh.cap * 8));
+    uint64_t *pool = pl.rerank ? reinterpret_cast<uint64_t *>(take((size_t)g * pl.need * 8)) : nullptr;
+    const DevIndex dix = ix->dev();
+    const DevCoarse dc{sc.ct, sc.cw, sc.cn, sc.qinv};
+    // retried rows are few: one query per workgroup
+    const int batch = kind == kPassSampled ? pl.batch : 1;
+    for (int64_t g0 = 0; g0 < n; g0 += g) {
+        const int32_t ns = (int32_t)std::min<int64_t>(g, n - g0);
+        const int32_t *sq = rows ? rows + g0 : slot_q;
+        if (!rows) HIP_TRY(launch_iota(slot_q, ns, (int32_t)g0, s));
+        if (sh.keep_all) {
+            HIP_TRY(launch_fill_f32(theta, ns, -INFINITY, s));
+        } else {
+            HIP_TRY(timed(kProfSample, s, [&] {
+                return launch_accumulate(dix, dq, dc, batch, true, sq, ns, sh.n_sample, maxima,
+                                         nullptr, nullptr, nullptr, 0, pl.tile_run, pl.max_qnnz, s);
+            }));
+            HIP_TRY(timed(kProfTheta, s, [&] {
+                return launch_theta(maxima, sh.n_max, sh.rank, ns, theta, s);
+            }));
+        }
+        HIP_TRY(launch_fill_u32(count, ns, 0u, s));
+        HIP_TRY(timed(kProfScore, s, [&] {
+            return launch_accumulate(dix, dq, dc, batch, false, sq, ns, 0, nullptr, theta, count,
+                                     cand, sh.cap, pl.tile_run, pl.max_qnnz, s);
+        }));
+        // without a threshold no sum is left implicit
+        HIP_TRY(timed(kProfFinal, s, [&] {
+            return launch_finalize(dix, dq, sq, ns, count, cand, sh.keep_all ? nullptr : theta,
+                                   sh.cap, pl.need, pl.k, pl.rerank, pl.max_qnnz, pool, out_ids,
+                                   out_scores, sc.status, s);
+        }));
+    }
+    return SINDI_OK;
+}
+
+sindi_status enqueue_collect_failed(const Scratch &sc, const int32_t *in_rows, int64_t n,
+                                    int32_t *out_rows, uint32_t *count, hipStream_t s)
+{
+    HIP_TRY(launch_collect_failed(sc.status, in_rows, (int32_t)n, out_rows, count, s));
+    return SINDI_OK;
+}
+
+sindi_status run_search(const sindi_index *ix, Scratch &sc, const Plan &plan, const DevQueries &dq,
+                        bool device_queries, int64_t *out_ids, float *out_scores, hipStream_t s,
+                        const char *fn, sindi_status (*grow)(void *, size_t, Scratch &),
+                        void *grow_ctx)
+{
+    Plan pl = plan;
+    const int64_t nq = dq.n_rows;
+    sindi_status st = enqueue_prep(ix, sc, pl, dq, s);
+    if (st != SINDI_OK) return st;
+    int32_t e2[2] = {0, 0};
+    if (device_queries) {
+        // validate before anything reaches the caller's outputs
+        HIP_TRY(hipMemcpyAsync(e2, sc.err, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (e2[0])
+            return fail(SINDI_E_INVALID,
+                        "%s: malformed query rows (flags 0x%x: 1 row pointers, 2 term id range, "
+                        "4 order, 8 non-finite, 16 more than %d entries)",
+                        fn, e2[0], kQueryHash / 2);
+        pl.max_qnnz = e2[1];
+    }
+    if ((st = enqueue_passes(ix, sc, pl, kPassSampled, dq, nullptr, nq, out_ids, out_scores, s)) != SINDI_OK)
+        return st;
+    if ((st = enqueue_collect_failed(sc, nullptr, nq, sc.rows, sc.n_rows, s)) != SINDI_OK) return st;
+    uint32_t n_fail = 0;
+    HIP_TRY(hipMemcpyAsync(&n_fail, sc.n_rows, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(e2, sc.err, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (e2[0]) return fail(SINDI_E_INTERNAL, "%s: validated host queries flagged 0x%x", fn, e2[0]);
+    // rows whose sampled threshold missed: a threshold over every tile, then no threshold
+    const PassKind retry[2] = {kPassFullSample, kPassKeepAll};
+    int32_t *lists[3] = {sc.rows, sc.rows2, sc.rows};
+    for (int r = 0; r < 2 && n_fail > 0; ++r) {
+        const size_t need = pass_bytes(pass_shape(ix, pl, retry[r]), pl, 1);
+        if (sc.arena_bytes < need) {
+            if (!grow) return fail(SINDI_E_INTERNAL, "%s: scratch too small for a retry", fn);
+            if ((st = grow(grow_ctx, need, sc)) != SINDI_OK) return st;
+        }
+        if ((st = enqueue_passes(ix, sc, pl, retry[r], dq, lists[r], n_fail, out_ids, out_scores,
+                                 s)) != SINDI_OK)
+            return st;
+        if ((st = enqueue_collect_failed(sc, lists[r], n_fail, lists[r + 1], sc.n_rows + 1, s)) != SINDI_OK)
+            return st;
+        HIP_TRY(hipMemcpyAsync(&n_fail, sc.n_rows + 1, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (n_fail) return fail(SINDI_E_INTERNAL, "%s: %u queries unresolved", fn, n_fail);
+    return SINDI_OK;
+}
+
+namespace {
+
+sindi_status grow_workspace(void *ctx, size_t bytes, Scratch &sc)
+{
+    Workspace &ws = *static_cast<Workspace *>(ctx);
+    HIP_TRY(ws.arena.ensure(bytes));
+    sc.arena = ws.arena.as<unsigned char>();
+    sc.arena_bytes = ws.arena.bytes;
+    return SINDI_OK;
+}
 
 sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
                          const sindi_search_params *pp, int64_t *out_ids, float *out_scores,
@@ -819,7 +913,14 @@ sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
     pl.max_qnnz = (int32_t)longest;
     std::lock_guard<std::mutex> lock(ix->mu);
     Workspace &ws = ix->ws;
-    if ((st = reserve_workspace(ws, pl, nq, qc->nnz)) != SINDI_OK) return st;
+    HIP_TRY(ws.row_part.ensure(scratch_row_bytes(pl, nq, qc->nnz)));
+    Scratch sc = carve_rows(ws.row_part.as<unsigned char>(), pl, nq, qc->nnz);
+    // the sampled pass in groups whose candidate buffers fit kCandBudget
+    const PassShape sh = pass_shape(ix, pl, kPassSampled);
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>(nq, pass_group(sh, pl, kCandBudget)));
+    HIP_TRY(ws.arena.ensure(pass_bytes(sh, pl, g)));
+    sc.arena = ws.arena.as<unsigned char>();
+    sc.arena_bytes = ws.arena.bytes;
 
     DevQueries dq{nq, qc->nnz, qc->indptr, qc->indices, qc->values};
     if (!qc->on_device) {
@@ -835,31 +936,8 @@ sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
         dq.indices = ws.q_idx.as<int32_t>();
         dq.values = ws.q_val.as<float>();
     }
-    if ((st = enqueue_prep(ix, ws, pl, dq, s)) != SINDI_OK) return st;
-    int32_t qerr = 0;
-    if (qc->on_device) {
-        // device queries: validate before anything reaches the caller's outputs
-        int32_t e2[2] = {0, 0};
-        HIP_TRY(hipMemcpyAsync(e2, ws.err.p, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        qerr = e2[0];
-        pl.max_qnnz = e2[1];
-        if (qerr)
-            return fail(SINDI_E_INVALID,
-                        "%s: malformed query rows (flags 0x%x: 1 row pointers, 2 term id range, "
-                        "4 order, 8 non-finite, 16 more than %d entries)",
-                        fn, qerr, kQueryHash / 2);
-    }
-    if ((st = enqueue_search(ix, ws, pl, dq, out_ids, out_scores, s)) != SINDI_OK) return st;
-    std::vector<int32_t> status((size_t)nq);
-    HIP_TRY(hipMemcpyAsync(status.data(), ws.status.p, (size_t)nq * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&qerr, ws.err.p, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (qerr) return fail(SINDI_E_INTERNAL, "%s: validated host queries flagged 0x%x", fn, qerr);
-    std::vector<int32_t> retry;
-    for (int64_t q = 0; q < nq; ++q)
-        if (status[q] != kSlotOk) retry.push_back((int32_t)q);
-    return retry_queries(ix, ws, pl, dq, retry, out_ids, out_scores, s, fn);
+    return run_search(ix, sc, pl, dq, qc->on_device != 0, out_ids, out_scores, s, fn,
+                      grow_workspace, &ws);
 }
 
 sindi_status check_dev_queries(sindi_index *ix, const sindi_csr *qc, const char *fn, hipStream_t s)
@@ -868,19 +946,18 @@ sindi_status check_dev_queries(sindi_index *ix, const sindi_csr *qc, const char 
     if (qc->n_cols != ix->n_cols) return fail(SINDI_E_INVALID, "%s: column count mismatch", fn);
     if (qc->n_rows < 0 || qc->nnz < 0) return fail(SINDI_E_INVALID, "%s: bad query shape", fn);
     if (qc->n_rows == 0) return SINDI_OK;
+    if (!qc->indptr || (qc->nnz > 0 && (!qc->indices || !qc->values)))
+        return fail(SINDI_E_INVALID, "%s: null query array", fn);
     Workspace &ws = ix->ws;
+    Plan pl;  // beta 1: no FP64 scratch
+    HIP_TRY(ws.row_part.ensure(scratch_row_bytes(pl, qc->n_rows, qc->nnz)));
+    const Scratch sc = carve_rows(ws.row_part.as<unsigned char>(), pl, qc->n_rows, qc->nnz);
     DevQueries dq{qc->n_rows, qc->nnz, qc->indptr, qc->indices, qc->values};
-    HIP_TRY(ws.ct.ensure((size_t)qc->nnz * 4 + 4));
-    HIP_TRY(ws.cw.ensure((size_t)qc->nnz * 4 + 4));
-    HIP_TRY(ws.cn.ensure((size_t)qc->n_rows * 4));
-    HIP_TRY(ws.qinv.ensure((size_t)qc->n_rows * 4));
-    HIP_TRY(ws.err.ensure(8));
-    HIP_TRY(launch_fill_u32(ws.err.as<uint32_t>(), 2, 0u, s));
-    DevCoarse dc{ws.ct.as<int32_t>(), ws.cw.as<float>(), ws.cn.as<int32_t>(), ws.qinv.as<float>()};
-    HIP_TRY(launch_query_prep(dq, ix->n_cols, 1.0, dc, ix->term_max.as<float>(), nullptr,
-                              ws.err.as<int32_t>(), s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(sc.err), 2, 0u, s));
+    DevCoarse dc{sc.ct, sc.cw, sc.cn, sc.qinv};
+    HIP_TRY(launch_query_prep(dq, ix->n_cols, 1.0, dc, ix->term_max.as<float>(), nullptr, sc.err, s));
     int32_t qerr = 0;
-    HIP_TRY(hipMemcpyAsync(&qerr, ws.err.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&qerr, sc.err, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (qerr) return fail(SINDI_E_INVALID, "%s: malformed query rows (flags 0x%x)", fn, qerr);
     return SINDI_OK;
@@ -999,8 +1076,8 @@ sindi_status sindi_search_coarse(const sindi_index *idx, const sindi_csr *querie
 }
 
 sindi_status sindi_score_forward(const sindi_index *idx, const sindi_csr *queries,
-                                 const int64_t *cand_ids, int32_t n_cand, float *out_scores,
-                                 void *stream)
+                                 const int64_t *cand_ids, int32_t n_cand,
+                                 const float *doc_values, float *out_scores, void *stream)
 {
     if (!idx || !queries || (!cand_ids && n_cand) || (!out_scores && n_cand) || n_cand < 0)
         return fail(SINDI_E_INVALID, "sindi_score_forward: bad argument");
@@ -1010,14 +1087,17 @@ sindi_status sindi_score_forward(const sindi_index *idx, const sindi_csr *querie
     sindi_status st = check_dev_queries(ix, queries, "sindi_score_forward", s);
     if (st != SINDI_OK) return st;
     DevQueries dq{queries->n_rows, queries->nnz, queries->indptr, queries->indices, queries->values};
-    HIP_TRY(launch_score_forward(ix->dev(), dq, cand_ids, n_cand, out_scores, s));
+    DevIndex dix = ix->dev();
+    if (doc_values) dix.values = doc_values;
+    HIP_TRY(launch_score_forward(dix, dq, cand_ids, n_cand, out_scores, s));
     return SINDI_OK;
 }
 
 sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queries,
                                   const int64_t *cand_ids, int32_t n_cand,
-                                  const float *grad_scores, float *grad_query_values,
-                                  float *grad_doc_values, void *stream)
+                                  const float *doc_values, const float *grad_scores,
+                                  float *grad_query_values, float *grad_doc_values,
+                                  void *stream)
 {
     if (!idx || !queries || (!cand_ids && n_cand) || (!grad_scores && n_cand) || n_cand < 0)
         return fail(SINDI_E_INVALID, "sindi_score_backward: bad argument");
@@ -1027,7 +1107,9 @@ sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queri
     sindi_status st = check_dev_queries(ix, queries, "sindi_score_backward", s);
     if (st != SINDI_OK) return st;
     DevQueries dq{queries->n_rows, queries->nnz, queries->indptr, queries->indices, queries->values};
-    HIP_TRY(launch_score_backward(ix->dev(), dq, cand_ids, n_cand, grad_scores, grad_query_values,
+    DevIndex dix = ix->dev();
+    if (doc_values) dix.values = doc_values;
+    HIP_TRY(launch_score_backward(dix, dq, cand_ids, n_cand, grad_scores, grad_query_values,
                                   grad_doc_values, s));
     return SINDI_OK;
 }

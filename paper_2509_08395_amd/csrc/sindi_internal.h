@@ -127,6 +127,11 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 // p[i] = first + i for i in [0, n).
 hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s);
 
+// Rows whose status is not kSlotOk (of [0, n), or of in_rows[0, n)) into
+// out_rows in order; their number into *count.
+hipError_t launch_collect_failed(const int32_t *status, const int32_t *in_rows, int32_t n,
+                                 int32_t *out_rows, uint32_t *count, hipStream_t s);
+
 // max_qnnz: bound on the length of every finalized query row (sizes the
 // rerank table; a longer row gets status kSlotRetry).  theta: the thresholds
 // the candidates were emitted with (null: every document was emitted); a

@@ -814,10 +814,12 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     int32_t l0, h0, l1, h1;
                     unpack_pair((uint32_t)r.x, (uint32_t)r.y, l0, h0);
                     unpack_pair((uint32_t)r.z, (uint32_t)r.w, l1, h1);
-                    const bool oa[2] = {any0 && m0 < len && l0 >= th0 && (!imp0 || l0 != 0),
-                                        any0 && m0 + 1 < len && l1 >= th0 && (!imp0 || l1 != 0)};
-                    const bool ob[2] = {any1 && m0 < len && h0 >= th1 && (!imp1 || h0 != 0),
-                                        any1 && m0 + 1 < len && h1 >= th1 && (!imp1 || h1 != 0)};
+                    // threshold <= 0: every nonzero sum, negative ones included, so that
+                    // the finalize kernel may take each document left out as a zero
+                    const bool oa[2] = {any0 && m0 < len && (imp0 ? l0 != 0 : l0 >= th0),
+                                        any0 && m0 + 1 < len && (imp0 ? l1 != 0 : l1 >= th0)};
+                    const bool ob[2] = {any1 && m0 < len && (imp1 ? h0 != 0 : h0 >= th1),
+                                        any1 && m0 + 1 < len && (imp1 ? h1 != 0 : h1 >= th1)};
                     if (__ballot(oa[0] || oa[1] || ob[0] || ob[1]) == 0) continue;
                     const float a[2] = {(float)l0 * qi0, (float)l1 * qi0};
                     const float b2[2] = {(float)h0 * qi1, (float)h1 * qi1};
@@ -1077,11 +1079,13 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                     const bool look = IMP ? ((r.x | r.y | r.z | r.w) != 0)
                                           : max(max(r.x, r.y), max(r.z, r.w)) >= th;
                     if (__ballot(look) == 0) continue;  // the common case
+                    // threshold <= 0: every nonzero sum, negative ones included (the
+                    // finalize kernel takes each document left out as a zero)
                     bool ok[4];
-                    ok[0] = r.x >= th && (!IMP || r.x != 0) && m0 < len;
-                    ok[1] = r.y >= th && (!IMP || r.y != 0) && m0 + 1 < len;
-                    ok[2] = r.z >= th && (!IMP || r.z != 0) && m0 + 2 < len;
-                    ok[3] = r.w >= th && (!IMP || r.w != 0) && m0 + 3 < len;
+                    ok[0] = (IMP ? r.x != 0 : r.x >= th) && m0 < len;
+                    ok[1] = (IMP ? r.y != 0 : r.y >= th) && m0 + 1 < len;
+                    ok[2] = (IMP ? r.z != 0 : r.z >= th) && m0 + 2 < len;
+                    ok[3] = (IMP ? r.w != 0 : r.w >= th) && m0 + 3 < len;
                     const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv, (float)r.z * qinv,
                                          (float)r.w * qinv};
                     emit_candidates<4>(sv, ok, d0 + m0, count + slot, cand + (size_t)slot * cap, cap);
@@ -1132,6 +1136,30 @@ __global__ void k_iota_i32(int32_t *p, int32_t n, int32_t first)
 {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         p[i] = first + i;
+}
+
+// Rows whose status is not kSlotOk, in order: of rows [0, n) (in_rows null)
+// or of in_rows[0, n).  One workgroup; writes the count last.
+__global__ __launch_bounds__(1024) void k_collect_failed(const int32_t *status,
+                                                         const int32_t *in_rows, int32_t n,
+                                                         int32_t *out_rows, uint32_t *count)
+{
+    __shared__ uint32_t s_wsum[1024 / kWave];
+    uint32_t base = 0;
+    for (int32_t i0 = 0; i0 < n; i0 += 1024) {
+        const int32_t i = i0 + (int32_t)threadIdx.x;
+        int32_t row = 0;
+        uint32_t bad = 0;
+        if (i < n) {
+            row = in_rows ? in_rows[i] : i;
+            bad = status[row] != kSlotOk ? 1u : 0u;
+        }
+        uint32_t tot;
+        const uint32_t pos = block_excl_scan<1024>(bad, s_wsum, tot);
+        if (bad) out_rows[base + pos] = row;
+        base += tot;
+    }
+    if (threadIdx.x == 0) *count = base;
 }
 
 // ------------------------------------------------------------------ finalize
@@ -1674,6 +1702,14 @@ hipError_t launch_iota(int32_t *p, int32_t n, int32_t first, hipStream_t s)
     int32_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect_failed(const int32_t *status, const int32_t *in_rows, int32_t n,
+                                 int32_t *out_rows, uint32_t *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_collect_failed, dim3(1), dim3(1024), 0, s, status, in_rows, n, out_rows,
+                       count);
     return hipGetLastError();
 }
 

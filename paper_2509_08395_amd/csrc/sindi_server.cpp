@@ -12,6 +12,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -64,18 +65,83 @@ template <typename T> struct Pinned {
     hipError_t alloc(size_t n) { return hipHostMalloc((void **)&p, (n ? n : 1) * sizeof(T), hipHostMallocDefault); }
 };
 
+// First-fit allocator over one device buffer: the candidate memory (sampled
+// maxima, candidate lists, rerank pools) shared by every batch in flight.  A
+// batch is admitted only when its share fits; used by the dispatcher thread
+// alone.
+struct Arena {
+    DBuf buf;
+    std::map<size_t, size_t> free_blocks;  // offset -> length, adjacent blocks merged
+    size_t used = 0, peak = 0;
+    static size_t round(size_t n) { return (n + 255) & ~(size_t)255; }
+    void reset()
+    {
+        free_blocks.clear();
+        free_blocks[0] = buf.bytes & ~(size_t)255;
+        used = peak = 0;
+    }
+    size_t largest() const
+    {
+        size_t m = 0;
+        for (const auto &b : free_blocks) m = std::max(m, b.second);
+        return m;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = round(bytes);
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_blocks.erase(it);
+            if (rest) free_blocks[at] = rest;
+            used += bytes;
+            peak = std::max(peak, used);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = round(bytes);
+        used -= bytes;
+        auto it = free_blocks.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_blocks.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_blocks.erase(next);
+        }
+        if (it != free_blocks.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_blocks.erase(it);
+            }
+        }
+    }
+};
+
+// One batch slot: its stream, completion event, device scratch and pinned
+// staging.  A batch moves through up to three stages, each ending with the
+// slot's event: the sampled pass over every request (stage 0), a pass with a
+// threshold taken over every tile for the rows whose sampled threshold missed
+// (stage 1), and a pass with no threshold for rows still unresolved (stage 2).
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    Workspace ws;
-    DBuf d_ids, d_scores;
+    DBuf q_ptr, q_idx, q_val, row_part, d_ids, d_scores;
+    Scratch sc;
+    size_t region_off = 0, region_bytes = 0;  // the batch's share of the arena (0: none)
+    bool wants_retry_buffer = false;          // a retry waits for the server's retry buffer
     Pinned<int64_t> h_ptr, h_ids;
-    Pinned<int32_t> h_idx, h_status, h_err;
+    Pinned<int32_t> h_idx, h_err;
+    Pinned<uint32_t> h_fail;  // [2] failed-row counts of the stages
     Pinned<float> h_val, h_scores;
     std::vector<Request *> reqs;
     Plan pl;
     DevQueries dq{};
     int32_t kb = 0;
+    int stage = 0;
     bool busy = false;
     sindi_status launch_st = SINDI_OK;
     std::string launch_msg;
@@ -98,7 +164,11 @@ struct sindi_server {
     const sindi_index *ix = nullptr;
     sindi_server_params p{};
     Plan base;                 // plan at k_max; batches differ only in k and size
-    int64_t group = 1;         // queries whose candidates fit one slot's workspace
+    PassShape main_shape;      // the sampled pass every batch runs
+    Arena arena;               // candidate memory of the batches in flight
+    DBuf retry_buf;            // one query of either retry pass; one slot at a time
+    Slot *retry_owner = nullptr;
+    bool mem_blocked = false;  // a batch is waiting for candidate memory
     std::vector<std::unique_ptr<Slot>> slots;
 
     std::mutex mu;
@@ -117,7 +187,10 @@ struct sindi_server {
 
     void run();
     bool launch(Slot &s, std::vector<Request *> &batch);
+    sindi_status enqueue_retry(Slot &s, PassKind kind, const int32_t *rows, uint32_t n,
+                               int32_t *out_rows, uint32_t *out_count, uint32_t *h_count);
     void complete(Slot &s);
+    void start_retry(Slot &s);
     void finish(Slot &s, sindi_status st, const std::string &msg);
 };
 
@@ -169,23 +242,26 @@ bool sindi_server::launch(Slot &s, std::vector<Request *> &batch)
     s.pl = base;
     s.pl.k = kb;
     s.pl.max_qnnz = longest;  // sizes the kernels' per-query LDS for this batch
-    s.pl.group = std::min<int64_t>(group, nb);
-    s.dq = DevQueries{nb, nnz, s.ws.q_ptr.as<int64_t>(), s.ws.q_idx.as<int32_t>(), s.ws.q_val.as<float>()};
+    s.stage = 0;
+    s.dq = DevQueries{nb, nnz, s.q_ptr.as<int64_t>(), s.q_idx.as<int32_t>(), s.q_val.as<float>()};
     auto enqueue = [&]() -> sindi_status {
         const hipStream_t st = s.stream;
-        HIP_TRY(hipMemcpyAsync(s.ws.q_ptr.p, s.h_ptr.p, (size_t)(nb + 1) * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(s.q_ptr.p, s.h_ptr.p, (size_t)(nb + 1) * 8, hipMemcpyHostToDevice, st));
         if (nnz) {
-            HIP_TRY(hipMemcpyAsync(s.ws.q_idx.p, s.h_idx.p, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
-            HIP_TRY(hipMemcpyAsync(s.ws.q_val.p, s.h_val.p, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(s.q_idx.p, s.h_idx.p, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(s.q_val.p, s.h_val.p, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
         }
-        sindi_status e = enqueue_prep(ix, s.ws, s.pl, s.dq, st);
+        sindi_status e = enqueue_prep(ix, s.sc, s.pl, s.dq, st);
         if (e != SINDI_OK) return e;
-        e = enqueue_search(ix, s.ws, s.pl, s.dq, s.d_ids.as<int64_t>(), s.d_scores.as<float>(), st);
+        e = enqueue_passes(ix, s.sc, s.pl, kPassSampled, s.dq, nullptr, nb, s.d_ids.as<int64_t>(),
+                           s.d_scores.as<float>(), st);
+        if (e != SINDI_OK) return e;
+        e = enqueue_collect_failed(s.sc, nullptr, nb, s.sc.rows, s.sc.n_rows, st);
         if (e != SINDI_OK) return e;
         HIP_TRY(hipMemcpyAsync(s.h_ids.p, s.d_ids.p, (size_t)nb * kb * 8, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(s.h_scores.p, s.d_scores.p, (size_t)nb * kb * 4, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(s.h_status.p, s.ws.status.p, (size_t)nb * 4, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(s.h_err.p, s.ws.err.p, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(s.h_fail.p, s.sc.n_rows, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(s.h_err.p, s.sc.err, 4, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipEventRecord(s.done, st));
         return SINDI_OK;
     };
@@ -193,6 +269,26 @@ bool sindi_server::launch(Slot &s, std::vector<Request *> &batch)
     s.launch_msg = s.launch_st == SINDI_OK ? std::string() : std::string(last_error());
     s.busy = true;
     return s.launch_st == SINDI_OK;
+}
+
+// Enqueue a retry stage of a slot's batch over the n device-listed rows:
+// the pass, the rows it still leaves unresolved (into out_rows / out_count),
+// the results and that count back to the host, then the slot's event.
+sindi_status sindi_server::enqueue_retry(Slot &s, PassKind kind, const int32_t *rows, uint32_t n,
+                                         int32_t *out_rows, uint32_t *out_count, uint32_t *h_count)
+{
+    const hipStream_t st = s.stream;
+    const int32_t nb = (int32_t)s.reqs.size();
+    sindi_status e = enqueue_passes(ix, s.sc, s.pl, kind, s.dq, rows, n, s.d_ids.as<int64_t>(),
+                                    s.d_scores.as<float>(), st);
+    if (e != SINDI_OK) return e;
+    e = enqueue_collect_failed(s.sc, rows, n, out_rows, out_count, st);
+    if (e != SINDI_OK) return e;
+    HIP_TRY(hipMemcpyAsync(s.h_ids.p, s.d_ids.p, (size_t)nb * s.kb * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(s.h_scores.p, s.d_scores.p, (size_t)nb * s.kb * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h_count, out_count, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(s.done, st));
+    return SINDI_OK;
 }
 
 // Hand the slot's results to its requests and free the slot.
@@ -229,46 +325,71 @@ void sindi_server::finish(Slot &s, sindi_status st, const std::string &msg)
     }
     stats.completed += (int64_t)s.reqs.size();
     s.reqs.clear();
+    if (s.region_bytes) arena.release(s.region_off, s.region_bytes);
+    s.region_bytes = 0;
+    if (retry_owner == &s) retry_owner = nullptr;
+    s.wants_retry_buffer = false;
     s.busy = false;
     if (--n_busy == 0)
         stats.busy_ms += std::chrono::duration<double, std::milli>(t1 - busy_since).count();
     cv_done.notify_all();
 }
 
-// The batch's event has fired: re-run any query whose candidate threshold
-// missed, then publish.
+// The slot's event has fired.  Rows whose candidate threshold missed are
+// retried on the slot's stream (the dispatcher does not wait for them): first
+// with a threshold over every tile, then with none; the batch is published
+// when no row is left.
 void sindi_server::complete(Slot &s)
 {
-    const int32_t nb = (int32_t)s.reqs.size();
-    if (s.h_err.p[0] != 0) {
+    if (s.stage == 0 && s.h_err.p[0] != 0) {
         finish(s, fail(SINDI_E_INTERNAL, "sindi_server: validated queries flagged 0x%x", s.h_err.p[0]),
                last_error());
         return;
     }
-    std::vector<int32_t> rows;
-    for (int32_t r = 0; r < nb; ++r)
-        if (s.h_status.p[r] != kSlotOk) rows.push_back(r);
-    if (!rows.empty()) {
-        auto redo = [&]() -> sindi_status {
-            sindi_status e = retry_queries(ix, s.ws, s.pl, s.dq, rows, s.d_ids.as<int64_t>(),
-                                           s.d_scores.as<float>(), s.stream, "sindi_server");
-            if (e != SINDI_OK) return e;
-            HIP_TRY(hipMemcpyAsync(s.h_ids.p, s.d_ids.p, (size_t)nb * s.kb * 8, hipMemcpyDeviceToHost, s.stream));
-            HIP_TRY(hipMemcpyAsync(s.h_scores.p, s.d_scores.p, (size_t)nb * s.kb * 4, hipMemcpyDeviceToHost, s.stream));
-            HIP_TRY(hipStreamSynchronize(s.stream));
-            return SINDI_OK;
-        };
-        const sindi_status e = redo();
+    // stage 0 and 2 leave their count in h_fail[0] (rows), stage 1 in h_fail[1] (rows2)
+    const uint32_t left = s.h_fail.p[s.stage == 1 ? 1 : 0];
+    if (left == 0) {
+        finish(s, SINDI_OK, std::string());
+        return;
+    }
+    if (s.stage == 2) {
+        finish(s, fail(SINDI_E_INTERNAL, "sindi_server: %u queries unresolved", left), last_error());
+        return;
+    }
+    if (s.stage == 0) {
         {
             std::lock_guard<std::mutex> lock(mu);
-            stats.retried += (int64_t)rows.size();
+            stats.retried += (int64_t)left;
         }
-        if (e != SINDI_OK) {
-            finish(s, e, last_error());
-            return;
-        }
+        // the sampled pass is done: its arena share goes back; retries run in the
+        // server's retry buffer, one batch at a time
+        arena.release(s.region_off, s.region_bytes);
+        s.region_bytes = 0;
     }
-    finish(s, SINDI_OK, std::string());
+    s.wants_retry_buffer = true;
+    start_retry(s);
+}
+
+// Enqueue the next retry stage of a slot's batch once the retry buffer is its.
+void sindi_server::start_retry(Slot &s)
+{
+    if (retry_owner && retry_owner != &s) return;  // the dispatcher tries again
+    retry_owner = &s;
+    s.wants_retry_buffer = false;
+    s.sc.arena = retry_buf.as<unsigned char>();
+    s.sc.arena_bytes = retry_buf.bytes;
+    sindi_status e;
+    if (s.stage == 0)
+        e = enqueue_retry(s, kPassFullSample, s.sc.rows, s.h_fail.p[0], s.sc.rows2, s.sc.n_rows + 1,
+                          s.h_fail.p + 1);
+    else
+        e = enqueue_retry(s, kPassKeepAll, s.sc.rows2, s.h_fail.p[1], s.sc.rows, s.sc.n_rows,
+                          s.h_fail.p);
+    s.stage += 1;
+    if (e != SINDI_OK) {
+        s.launch_st = e;  // the dispatcher drains the stream and publishes the error
+        s.launch_msg = last_error();
+    }
 }
 
 void sindi_server::run()
@@ -276,10 +397,14 @@ void sindi_server::run()
     (void)hipSetDevice(ix->device);
     std::vector<Request *> batch;
     for (;;) {
-        // publish finished batches
+        // publish finished batches, and start waiting retries
         for (auto &sp : slots) {
             Slot &s = *sp;
             if (!s.busy) continue;
+            if (s.wants_retry_buffer && s.launch_st == SINDI_OK) {
+                start_retry(s);
+                continue;
+            }
             if (s.launch_st != SINDI_OK) {
                 // the stream may still hold part of the batch: drain it first
                 (void)hipStreamSynchronize(s.stream);
@@ -294,8 +419,10 @@ void sindi_server::run()
             else
                 complete(s);
         }
-        // start the next batch on a free slot
+        // start the next batch on a free slot: as many queued requests as the largest
+        // free block of candidate memory holds (at most max_batch)
         Slot *free_slot = nullptr;
+        size_t region = 0, off = 0;
         {
             std::unique_lock<std::mutex> lock(mu);
             bool any_busy = false;
@@ -304,20 +431,37 @@ void sindi_server::run()
                 else if (!free_slot) free_slot = sp.get();
             }
             if (stop && !any_busy) return;
-            if (stop || pending.empty() || !free_slot) {
+            int64_t fit = 0;
+            if (!stop && !pending.empty() && free_slot) {
+                fit = std::min<int64_t>(pass_group(main_shape, base, arena.largest()),
+                                        std::min<int64_t>((int64_t)pending.size(), p.max_batch));
+                if (fit < 1 && !mem_blocked) stats.memory_waits += 1;  // in-flight batches hold it
+                mem_blocked = fit < 1;
+            }
+            if (fit < 1) {
                 if (any_busy) cv_work.wait_for(lock, std::chrono::microseconds(20));
                 else cv_work.wait(lock, [&] { return stop || !pending.empty(); });
                 continue;
             }
             batch.clear();
-            while (!pending.empty() && (int32_t)batch.size() < p.max_batch) {
+            while ((int64_t)batch.size() < fit) {
                 batch.push_back(pending.front());
                 pending.pop_front();
             }
+            region = pass_bytes(main_shape, base, fit);
+            if (!arena.alloc(region, &off)) {  // cannot happen: fit came from the largest block
+                for (auto it = batch.rbegin(); it != batch.rend(); ++it) pending.push_front(*it);
+                continue;
+            }
             stats.batches += 1;
             stats.largest_batch = std::max<int64_t>(stats.largest_batch, (int64_t)batch.size());
+            stats.arena_peak_bytes = std::max<int64_t>(stats.arena_peak_bytes, (int64_t)arena.peak);
             if (n_busy++ == 0) busy_since = Clock::now();
         }
+        free_slot->region_off = off;
+        free_slot->region_bytes = region;
+        free_slot->sc.arena = arena.buf.as<unsigned char>() + off;
+        free_slot->sc.arena_bytes = region;
         launch(*free_slot, batch);
     }
 }
@@ -335,7 +479,7 @@ sindi_status create_impl(const sindi_index *ix, const sindi_server_params *pp, s
     if (!p.k_max) p.k_max = 100;
     if (!p.max_query_nnz) p.max_query_nnz = 512;
     if (!p.max_queue) p.max_queue = (int64_t)1 << 20;
-    if (!p.workspace_bytes) p.workspace_bytes = (int64_t)1 << 30;
+    if (!p.workspace_bytes) p.workspace_bytes = (int64_t)2 << 30;
     if (p.max_inflight < 1 || p.max_inflight > kMaxSlots)
         return fail(SINDI_E_INVALID, "sindi_server_create: max_inflight must be in [1, %d]", kMaxSlots);
     if (p.max_batch < 1 || p.max_batch > kMaxBatchQueries)
@@ -352,25 +496,32 @@ sindi_status create_impl(const sindi_index *ix, const sindi_server_params *pp, s
     sindi_status st = make_plan(ix, p.max_batch, p.k_max, p.search, true, "sindi_server_create", srv->base);
     if (st != SINDI_OK) return st;
     srv->base.max_qnnz = p.max_query_nnz;
-    srv->group = std::max<int64_t>(
-        1, std::min<int64_t>(p.max_batch, p.workspace_bytes / (int64_t)plan_query_bytes(srv->base)));
-    srv->base.group = srv->group;
+    // candidate memory shared by the batches in flight (at least one query), and a
+    // retry buffer for one query of either retry pass
+    const Plan &pl = srv->base;
+    srv->main_shape = pass_shape(ix, pl, kPassSampled);
+    const size_t arena = std::max<size_t>((size_t)p.workspace_bytes, pass_bytes(srv->main_shape, pl, 1));
+    const size_t retry = std::max(pass_bytes(pass_shape(ix, pl, kPassFullSample), pl, 1),
+                                  pass_bytes(pass_shape(ix, pl, kPassKeepAll), pl, 1));
 
     int prev = 0;
     HIP_TRY(hipGetDevice(&prev));
     HIP_TRY(hipSetDevice(ix->device));
     auto alloc = [&]() -> sindi_status {
+        HIP_TRY(srv->arena.buf.ensure(arena));
+        srv->arena.reset();
+        HIP_TRY(srv->retry_buf.ensure(retry));
         const size_t mb = (size_t)p.max_batch, qn = mb * (size_t)p.max_query_nnz, kk = (size_t)p.k_max;
         for (int i = 0; i < p.max_inflight; ++i) {
             srv->slots.emplace_back(new Slot());
             Slot &s = *srv->slots.back();
             HIP_TRY(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
             HIP_TRY(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
-            sindi_status e = reserve_workspace(s.ws, srv->base, p.max_batch, (int64_t)qn);
-            if (e != SINDI_OK) return e;
-            HIP_TRY(s.ws.q_ptr.ensure((mb + 1) * 8));
-            HIP_TRY(s.ws.q_idx.ensure(qn * 4 + 4));
-            HIP_TRY(s.ws.q_val.ensure(qn * 4 + 4));
+            HIP_TRY(s.row_part.ensure(scratch_row_bytes(pl, p.max_batch, (int64_t)qn)));
+            s.sc = carve_rows(s.row_part.as<unsigned char>(), pl, p.max_batch, (int64_t)qn);
+            HIP_TRY(s.q_ptr.ensure((mb + 1) * 8));
+            HIP_TRY(s.q_idx.ensure(qn * 4 + 4));
+            HIP_TRY(s.q_val.ensure(qn * 4 + 4));
             HIP_TRY(s.d_ids.ensure(mb * kk * 8));
             HIP_TRY(s.d_scores.ensure(mb * kk * 4));
             HIP_TRY(s.h_ptr.alloc(mb + 1));
@@ -378,7 +529,7 @@ sindi_status create_impl(const sindi_index *ix, const sindi_server_params *pp, s
             HIP_TRY(s.h_val.alloc(qn));
             HIP_TRY(s.h_ids.alloc(mb * kk));
             HIP_TRY(s.h_scores.alloc(mb * kk));
-            HIP_TRY(s.h_status.alloc(mb));
+            HIP_TRY(s.h_fail.alloc(2));
             HIP_TRY(s.h_err.alloc(1));
         }
         return SINDI_OK;

@@ -80,29 +80,61 @@ struct DBuf {
     template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
-// Device scratch of one search in flight: device copies of host queries,
-// coarse query terms, per-query status, the sampled maxima and thresholds,
-// and the per-query candidate lists ("score windows" leaving LDS).
-struct Workspace {
-    DBuf q_ptr, q_idx, q_val, ct, cw, cn, qinv, sabs, err, status, slot_q, maxima, theta, count,
-        cand, pool;
-};
-
 // The parameters of one search, resolved against the index.
 struct Plan {
     int32_t k = 0, gamma = 0, need = 0, batch = 1, n_sample = 0, tile_run = 0;
     int32_t max_qnnz = 0;  // bound on every query row's length (rerank table size)
-    int64_t cap = 0, rank = 0, n_max = 0, group = 0;
+    int64_t cap = 0, rank = 0;
     bool keep_all = true, rerank = true;
     double beta = 1.0;
 };
 
-// Bytes of device scratch one query needs under a plan (candidates, maxima,
-// rerank pool, threshold, count, status).
-inline size_t plan_query_bytes(const Plan &pl)
-{
-    return (size_t)pl.cap * 8 + (size_t)pl.n_max * 4 + (pl.rerank ? (size_t)pl.need * 8 : 0) + 16;
-}
+// Device scratch of one search as raw pointers into memory owned elsewhere (a
+// Workspace, a server slot, or the library's static scratch array).  The row
+// part holds one entry per query row (or per query entry) of the call; the
+// arena holds, for one group of query slots at a time, what a pass keeps per
+// slot: the slot's row, candidate count, threshold, sampled maxima, candidate
+// list and rerank pool.
+struct Scratch {
+    int32_t *ct = nullptr, *cn = nullptr, *err = nullptr, *status = nullptr;
+    int32_t *rows = nullptr, *rows2 = nullptr;  // failed rows, two lists for two retries
+    uint32_t *n_rows = nullptr;                 // [2] lengths of rows / rows2
+    float *cw = nullptr, *qinv = nullptr;
+    double *sabs = nullptr;
+    unsigned char *arena = nullptr;
+    size_t arena_bytes = 0;
+};
+
+// Bytes of the row part of a Scratch for nq rows of nnz entries in total.
+size_t scratch_row_bytes(const Plan &pl, int64_t nq, int64_t nnz);
+// Lay the row part out at p (256-byte aligned pieces); the arena is left empty.
+Scratch carve_rows(unsigned char *p, const Plan &pl, int64_t nq, int64_t nnz);
+
+// How a pass finds each query's coarse candidates:
+//   kPassSampled     threshold = the rank-th largest per-thread maximum over
+//                    the plan's evenly spaced sample tiles (may miss: then
+//                    the query is retried);
+//   kPassFullSample  the same over every tile with rank = gamma, so at least
+//                    gamma documents reach the threshold (misses only if more
+//                    than the candidate buffer reach it);
+//   kPassKeepAll     no threshold, every document is a candidate.
+enum PassKind { kPassSampled = 0, kPassFullSample = 1, kPassKeepAll = 2 };
+struct PassShape {
+    int32_t n_sample = 0;
+    int64_t n_max = 0, rank = 0, cap = 0;
+    bool keep_all = false;
+};
+PassShape pass_shape(const sindi_index *ix, const Plan &pl, PassKind kind);
+// Arena bytes of g query slots of a pass.
+size_t pass_bytes(const PassShape &sh, const Plan &pl, int64_t g);
+// Most query slots of a pass that an arena of `bytes` holds (0 if not one).
+int64_t pass_group(const PassShape &sh, const Plan &pl, size_t bytes);
+
+// Grow-only owner of a Scratch (sindi_search's, one per index).
+struct Workspace {
+    DBuf q_ptr, q_idx, q_val, row_part, arena;
+    Scratch view;
+};
 
 enum { kProfPrep = 0, kProfSample = 1, kProfScore = 2, kProfTheta = 3, kProfFinal = 4 };
 // Launch through `fn`, bracketed by HIP events on s while profiling is on.
@@ -145,26 +177,34 @@ sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
 sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max_row,
                                int64_t *longest = nullptr);
 
-// Size ws for nq queries of total nnz under pl (allocations; not async).
-sindi_status reserve_workspace(Workspace &ws, const Plan &pl, int64_t nq, int64_t nnz);
-
 // Enqueue on s the query preparation of rows [0, nq) of dq: beta-mass
 // coarse terms, fixed-point weights and device-side validation, whose flags
-// land in ws.err[0] (0: every row well formed), the longest row in ws.err[1].
-// No host sync.
-sindi_status enqueue_prep(const sindi_index *ix, Workspace &ws, const Plan &pl,
+// land in sc.err[0] (0: every row well formed), the longest row in sc.err[1].
+sindi_status enqueue_prep(const sindi_index *ix, const Scratch &sc, const Plan &pl,
                           const DevQueries &dq, hipStream_t s);
 
-// Enqueue on s, after enqueue_prep, every accumulate / threshold / finalize
-// launch of the plan.  Per-query status lands in ws.status.  No host sync.
-sindi_status enqueue_search(const sindi_index *ix, Workspace &ws, const Plan &pl,
-                            const DevQueries &dq, int64_t *out_ids, float *out_scores,
-                            hipStream_t s);
+// Enqueue on s, after enqueue_prep, passes of one kind over n query rows:
+// rows [0, n) of dq when rows is null, else the rows listed in device memory
+// rows[0, n).  Slots go in groups that fit sc's arena (at least one must).
+// Each row's status lands in sc.status; results in the row's output rows.
+sindi_status enqueue_passes(const sindi_index *ix, const Scratch &sc, const Plan &pl,
+                            PassKind kind, const DevQueries &dq, const int32_t *rows, int64_t n,
+                            int64_t *out_ids, float *out_scores, hipStream_t s);
 
-// Re-run, with every document kept, the listed query rows whose threshold
-// missed (status kSlotRetry).  Synchronous.
-sindi_status retry_queries(const sindi_index *ix, Workspace &ws, const Plan &pl,
-                           const DevQueries &dq, const std::vector<int32_t> &rows,
-                           int64_t *out_ids, float *out_scores, hipStream_t s, const char *fn);
+// Enqueue the compaction of the rows whose status is not kSlotOk: of rows
+// [0, n) (in_rows null) or of in_rows[0, n), into out_rows, the count into
+// *count (device).
+sindi_status enqueue_collect_failed(const Scratch &sc, const int32_t *in_rows, int64_t n,
+                                    int32_t *out_rows, uint32_t *count, hipStream_t s);
+
+// Synchronous search of validated device queries dq with the scratch sc:
+// prep, sampled (or keep-all) passes, then for rows whose threshold missed a
+// pass over every tile and, for rows still unresolved, a keep-all pass.  The
+// arena is regrown through grow (may be null: then sc's arena must hold one
+// keep-all query).  Device queries are validated on the device first.
+sindi_status run_search(const sindi_index *ix, Scratch &sc, const Plan &pl, const DevQueries &dq,
+                        bool device_queries, int64_t *out_ids, float *out_scores, hipStream_t s,
+                        const char *fn, sindi_status (*grow)(void *, size_t, Scratch &),
+                        void *grow_ctx);
 
 }  // namespace sindi

@@ -94,3 +94,41 @@ def pool_margin_fn(pool_ids, pool_sc, pruned_corpus, queries, rtol):
         sc = score_scale(pruned_corpus, queries, [r, r], [d, lastid]).max()
         return abs(c - last) <= 2 * rtol * sc
     return f
+
+
+def stored_value_bits(values, dtype):
+    """The bits the index must hold for FP32 values stored as dtype: FP32 copied, FP16 and
+    BF16 rounded to nearest even (numpy's and torch's conversions)."""
+    values = np.ascontiguousarray(values, np.float32)
+    if dtype == "f32":
+        return values.view(np.uint32)
+    if dtype == "f16":
+        return values.astype(np.float16).view(np.uint16)
+    import torch
+    return torch.from_numpy(values.copy()).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+
+
+def check_layout_against_oracle(ex, ref, n_cols, window, dtype):
+    """An exported index (pads dropped) holds Alg. 1's lists over the oracle's kept entries:
+    per (term, window) the same documents, ascending inside every (tile, term) list, tiles
+    inside windows, and each posting's value bits as stored_value_bits of the oracle's value."""
+    tile_doc, tile_post, term_off = ex["tile_doc"], ex["tile_post"], ex["term_off"]
+    nt = tile_doc.shape[0] - 1
+    assert tile_doc[0] == 0 and tile_doc[-1] == ref.n_docs
+    if nt:
+        assert (np.diff(tile_doc) > 0).all()
+        assert ((tile_doc[:-1] // window) == ((tile_doc[1:] - 1) // window)).all()
+    tile_of = np.repeat(np.arange(nt), np.diff(tile_post))
+    term_of = np.repeat(np.tile(np.arange(n_cols), nt), np.diff(term_off, axis=1).ravel())
+    doc = ex["post_doc"].astype(np.int64) + tile_doc[tile_of]
+    assert doc.shape[0] == ref.doc.shape[0], (doc.shape[0], ref.doc.shape[0])
+    order = np.lexsort((doc, doc // window, term_of))  # Alg. 1 order: term, window, document
+    assert np.array_equal(doc[order], ref.doc.astype(np.int64))
+    ref_term = (np.repeat(np.arange(n_cols), np.diff(ref.ptr[::ref.sigma])) if ref.sigma
+                else np.zeros(0, np.int64))
+    assert np.array_equal(term_of[order], ref_term)
+    same = (tile_of[1:] == tile_of[:-1]) & (term_of[1:] == term_of[:-1])
+    assert (np.diff(doc)[same] > 0).all()
+    got = np.ascontiguousarray(ex["post_val"])
+    got = got.view(np.uint32) if dtype == "f32" else got.view(np.uint16)
+    assert np.array_equal(got[order], stored_value_bits(ref.val, dtype))

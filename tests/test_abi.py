@@ -28,6 +28,21 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in lib.sindi_version()
 
 
+def test_probe_library_exports_its_header_and_checks_arguments():
+    """The LDS microbenchmark library exports exactly what include/sindi_probe.h declares
+    and refuses bad arguments before any device work."""
+    import ctypes as C
+    from paper_2509_08395_amd import _lib
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "sindi_probe.h")).read(),
+                  flags=re.S)
+    names = sorted(set(re.findall(r"\b(sindi_[a-z_]+)\s*\(", text)))
+    assert names == sorted(_lib.PROBE_EXPORTS)
+    lib = _lib.load_probe()
+    ms, upd = C.c_double(), C.c_double()
+    for args in ((2, 1, 1, 1), (0, -1, 1, 1), (0, 1, 0, 1), (0, 1, 1, 0)):
+        assert lib.sindi_probe_lds_add(*args, None, C.byref(ms), C.byref(upd)) != 0
+
+
 def test_no_cpu_fallback_in_package():
     """The product path has no route to the oracle or to a CPU implementation."""
     pkg = os.path.join(ROOT, "paper_2509_08395_amd")
@@ -88,7 +103,9 @@ def test_null_arguments_are_errors_not_crashes():
     assert lib.sindi_build(None, None, None, None) == _lib.SINDI_E_INVALID
     assert lib.sindi_search(None, None, 10, None, None, None, None) == _lib.SINDI_E_INVALID
     assert lib.sindi_index_get_info(None, None) == _lib.SINDI_E_INVALID
-    assert lib.sindi_score_forward(None, None, None, 0, None, None) == _lib.SINDI_E_INVALID
+    assert lib.sindi_score_forward(None, None, None, 0, None, None, None) == _lib.SINDI_E_INVALID
+    assert lib.sindi_score_backward(None, None, None, 0, None, None, None, None,
+                                    None) == _lib.SINDI_E_INVALID
     lib.sindi_index_free(None)
 
 
@@ -147,3 +164,22 @@ def test_build_rejects_bad_pruning_parameters(prune, vn, list_len):
     h = ctypes.c_void_p()
     assert lib.sindi_build(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(h)) == _lib.SINDI_E_INVALID
     assert not h.value
+
+
+def test_score_arguments_are_checked_before_the_library_is_called():
+    """The score kernels index cand, grad and the gradient buffers by the query count, the
+    candidate count and the corpus size, which the C side cannot see: the binding refuses
+    mis-shaped or misplaced tensors first (here CPU tensors, so nothing reaches a GPU)."""
+    import torch
+    import paper_2509_08395_amd as sindi
+    idx = sindi.Index.__new__(sindi.Index)
+    idx._h, idx.nnz, idx.n_cols = None, 10, 5
+    dq = sindi.DeviceCsr(torch.zeros(3, dtype=torch.int64), torch.zeros(0, dtype=torch.int32),
+                         torch.zeros(0), 5)
+    E = sindi.SindiError
+    with pytest.raises(E, match="DeviceCsr"):
+        idx.score(object(), torch.zeros((2, 3), dtype=torch.int64))
+    with pytest.raises(E, match="cand"):
+        idx.score(dq, torch.zeros((2, 3), dtype=torch.int64))
+    with pytest.raises(E, match="cand"):
+        idx.score_backward(dq, torch.zeros((3, 3), dtype=torch.int64), torch.zeros((3, 3)))

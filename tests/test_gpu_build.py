@@ -1,10 +1,13 @@
-"""The index built on the device equals the host build bit for bit (Alg. 3 pruning, then
-Alg. 1's lists in the tiled 4-slot-aligned layout), for every storage type and the pruning
-rules it supports, and rejects what the host rejects."""
+"""The index built on the device holds exactly the oracle's Alg. 3 pruning followed by its
+Alg. 1 lists (every storage type, MRP and VNP, rows longer than one wave's 512 entries,
+signed values, explicit zeros, empty rows), equals the host build bit for bit in the tiled
+4-slot-aligned layout, and rejects what the host rejects."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
+from parity import check_layout_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +41,12 @@ def _same_search(a, b, queries, k=20, gamma=200):
     assert torch.equal(sa.view(torch.int32), sb.view(torch.int32))
 
 
+def _oracle_keep(corpus, prune, kw):
+    if prune == "mrp":
+        return oracle.mass_prune(corpus, kw["alpha"])
+    return oracle.vnp_prune(corpus, kw["vn"])
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("prune,kw", [("mrp", dict(alpha=0.5)), ("mrp", dict(alpha=1.0)),
                                       ("vnp", dict(vn=17))])
@@ -48,6 +57,11 @@ def test_device_build_equals_host_build(sindi, dtype, prune, kw):
     g = sindi.Index(corpus, window=7_000, value_dtype=dtype, tile=2_048, prune=prune, gpu_build=True, **kw)
     _same_index(h, g)
     _same_search(h, g, queries)
+    # Alg. 3 then Alg. 1 as the oracle computes them
+    keep = _oracle_keep(corpus, prune, kw)
+    assert g.info()["n_postings"] == int(keep.sum())
+    check_layout_against_oracle(g.export(), oracle.build_index(corpus, 7_000, keep), 2_000, 7_000,
+                                dtype)
 
 
 def test_device_build_vocabulary_over_one_pass(sindi):
@@ -82,6 +96,8 @@ def test_device_build_degenerate_corpora(sindi):
         g = sindi.Index(c, alpha=0.5, window=4, gpu_build=True)
         _same_index(h, g)
         _same_search(h, g, queries, k=3, gamma=3)
+        check_layout_against_oracle(g.export(), oracle.build_index(c, 4, oracle.mass_prune(c, 0.5)),
+                                    50, 4, "f32")
 
 
 def test_device_build_long_rows_signed_zeros_and_empty_rows(sindi):
@@ -97,11 +113,21 @@ def test_device_build_long_rows_signed_zeros_and_empty_rows(sindi):
     lens = np.diff(c.indptr)
     assert (lens > 512).sum() >= 30 and (lens == 0).any()
     queries = synth.random_csr(rng, 24, 6_000, 40, signed=True, min_nnz=1)
-    for prune, kw in (("mrp", dict(alpha=0.6)), ("vnp", dict(vn=300))):
-        h = sindi.Index(c, window=1_500, tile=700, prune=prune, **kw)
-        g = sindi.Index(c, window=1_500, tile=700, prune=prune, gpu_build=True, **kw)
-        _same_index(h, g)
-        _same_search(h, g, queries)
+    for prune, kw in (("mrp", dict(alpha=0.6)), ("vnp", dict(vn=300)), ("mrp", dict(alpha=1.0))):
+        for dtype in ("f32", "bf16"):
+            h = sindi.Index(c, window=1_500, tile=700, prune=prune, value_dtype=dtype, **kw)
+            g = sindi.Index(c, window=1_500, tile=700, prune=prune, value_dtype=dtype,
+                            gpu_build=True, **kw)
+            _same_index(h, g)
+            _same_search(h, g, queries)
+            # against the oracle: rows over 512 entries take the one-workgroup pruning path;
+            # explicit zeros are no entries and never kept; negative values rank by |x|
+            keep = _oracle_keep(c, prune, kw)
+            assert not keep[c.values == 0.0].any()
+            assert keep[np.repeat(lens > 512, lens)].sum() > 0
+            assert g.info()["n_postings"] == int(keep.sum())
+            check_layout_against_oracle(g.export(), oracle.build_index(c, 1_500, keep), 6_000,
+                                        1_500, dtype)
 
 
 def test_device_build_from_device_corpus(sindi):
@@ -112,6 +138,9 @@ def test_device_build_from_device_corpus(sindi):
                     tile=1_024, gpu_build=True)
     _same_index(h, g)
     _same_search(h, g, queries)
+    check_layout_against_oracle(g.export(), oracle.build_index(corpus, 5_000,
+                                                               oracle.mass_prune(corpus, 0.5)),
+                                3_000, 5_000, "f16")
 
 
 def test_device_build_rejections(sindi):

@@ -101,3 +101,86 @@ def test_autograd_loss_and_gradients(sindi, setup):
     np.testing.assert_allclose(gq, rq, rtol=1e-4, atol=1e-5 * np.abs(rq).max())
     touched = np.nonzero(rx)[0]
     np.testing.assert_allclose(gx[touched], rx[touched], rtol=1e-4, atol=1e-5 * np.abs(rx).max())
+
+
+def _loss(scores, pos, tau):
+    """Softmax contrastive loss over each query's candidates (FP64), and dL/ds."""
+    z = scores.astype(np.float64) / tau
+    m = z.max(axis=1, keepdims=True)
+    e = np.exp(z - m)
+    p = e / e.sum(axis=1, keepdims=True)
+    rows = np.arange(z.shape[0])
+    loss = float(np.mean(np.log(e.sum(axis=1)) + m[:, 0] - z[rows, pos]))
+    G = p.copy()
+    G[rows, pos] -= 1.0
+    return loss, G / (tau * z.shape[0])
+
+
+def test_backward_kernel_against_finite_differences_on_the_gpu(sindi, setup):
+    """Central differences of the loss through the GPU forward kernel (FP32 scores, loss in
+    FP64 on the host), on sampled query and document coordinates, against the GPU backward
+    kernel.  Each score is linear in each coordinate and the loss is smooth in the scores, so
+    the step h = 1/32 keeps the central difference's curvature error near 1e-4 while the
+    rounding of the FP32 scores stays near 5e-4 of the difference (a step of 1e-3 would drown
+    in that rounding; the oracle itself is checked with h = 1e-3 in FP64).  Tolerance: 1e-2
+    of the gradient plus 1e-4 of the largest one.  Coordinates outside every (query,
+    candidate) intersection must have a zero gradient and an exactly zero difference."""
+    wl, corpus, queries, idx, cand, at, ids, sc, found = setup
+    tau = wl.extra["tau"]
+    dq = sindi.DeviceCsr.from_host(queries)
+    tc = torch.from_numpy(cand).cuda()
+    qv = torch.from_numpy(queries.values.copy()).cuda()
+    xv = torch.from_numpy(corpus.values.copy()).cuda()
+
+    def loss_at(qvals, xvals):
+        s = idx.score(sindi.DeviceCsr(dq.indptr, dq.indices, qvals, queries.n_cols), tc,
+                      doc_values=xvals)
+        return _loss(s.cpu().numpy(), at, tau)
+
+    L0, G = loss_at(qv, xv)
+    gq = torch.zeros(queries.nnz, device="cuda")
+    gx = torch.zeros(corpus.nnz, device="cuda")
+    idx.score_backward(dq, tc, torch.from_numpy(G.astype(np.float32)).cuda(), gq, gx,
+                       doc_values=xv)
+    gq, gx = gq.cpu().numpy(), gx.cpu().numpy()
+    rng = np.random.default_rng(77)
+    h = 1.0 / 32
+    q_nz = np.nonzero(np.abs(gq) > 1e-3 * np.abs(gq).max())[0]
+    x_nz = np.nonzero(np.abs(gx) > 1e-3 * np.abs(gx).max())[0]
+    # entries of candidate documents that no query shares
+    rows_c = np.unique(cand)
+    ents = np.concatenate([np.arange(corpus.indptr[d], corpus.indptr[d + 1]) for d in rows_c[:200]])
+    x_zero = rng.choice(ents[gx[ents] == 0], 16, replace=False)
+    checks = ([("q", e) for e in rng.choice(q_nz, 48, replace=False)] +
+              [("x", e) for e in rng.choice(x_nz, 48, replace=False)] +
+              [("x", e) for e in x_zero])
+    gmax = {"q": np.abs(gq).max(), "x": np.abs(gx).max()}
+    for side, e in checks:
+        base = qv if side == "q" else xv
+        plus, minus = base.clone(), base.clone()
+        plus[e] += h
+        minus[e] -= h
+        if side == "q":
+            fd = (loss_at(plus, xv)[0] - loss_at(minus, xv)[0]) / (2 * h)
+            g = gq[e]
+        else:
+            fd = (loss_at(qv, plus)[0] - loss_at(qv, minus)[0]) / (2 * h)
+            g = gx[e]
+        if g == 0.0:
+            assert fd == 0.0, (side, e, fd)
+        else:
+            assert abs(fd - g) <= 1e-2 * abs(g) + 1e-4 * gmax[side], (side, e, fd, g)
+
+
+def test_autograd_scores_the_document_values_passed(sindi, setup):
+    """SindiScore takes the document values as an input: doubling them doubles every score
+    and halves nothing else (the index's build-time copy is not what it scores)."""
+    wl, corpus, queries, idx, cand, at, ids, sc, found = setup
+    qv = torch.from_numpy(queries.values.copy()).cuda()
+    xv = torch.from_numpy(corpus.values.copy()).cuda()
+    qp = torch.from_numpy(queries.indptr.astype(np.int64)).cuda()
+    qi = torch.from_numpy(queries.indices.astype(np.int32)).cuda()
+    tc = torch.from_numpy(cand).cuda()
+    s1 = sindi.SindiScore.apply(qv, xv, idx, qp, qi, tc)
+    s2 = sindi.SindiScore.apply(qv, 2 * xv, idx, qp, qi, tc)
+    assert torch.equal(s2, 2 * s1)

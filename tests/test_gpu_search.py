@@ -467,3 +467,121 @@ def test_pruning_rules_layout_and_search(sindi, small, prune, kw):
     cp = oracle.apply_mask(corpus, keep)
     check_same_topk(ids, rid, rsc, _tol_kth(corpus, queries, rid, rsc, 1e-5),
                     pool_margin=pool_margin_fn(pid, psc, cp, queries, 1e-5))
+
+
+def test_negative_sums_below_a_zero_threshold(sindi):
+    """Signed data where fewer than gamma documents score above 0 (the sampled threshold
+    is 0): the lowest-id documents score below 0 and must rank after every zero-score
+    document (Alg. 2's heap orders by score before id), both in the coarse top-k (Alg. 2,
+    k = gamma) and in Alg. 4's pool (k = gamma), as the oracle computes them."""
+    rng = np.random.default_rng(41)
+    n, vocab, planted = 40_000, 2_000, 1_999
+    base = synth.random_csr(rng, n, vocab - 1, 8, signed=True, min_nnz=1)
+    # documents 0..59 also hold the last term, with a negative value (appended at each
+    # row's end keeps the term ids ascending)
+    at = base.indptr[1:61]
+    indptr = base.indptr + np.minimum(np.arange(n + 1), 60)
+    corpus = synth.Csr(indptr, np.insert(base.indices, at, planted),
+                       np.insert(base.values, at, -(0.5 + rng.random(60)).astype(np.float32)),
+                       vocab)
+    cnt = np.bincount(base.indices, minlength=vocab)
+    rare = np.argsort(cnt[:vocab - 1], kind="stable")[:100]
+    qrows = []
+    for b in range(12):
+        t = np.sort(rng.choice(rare, size=1 + b % 2, replace=False))
+        d = dict(zip(t.tolist(), rng.lognormal(0.0, 0.8, size=t.size).astype(np.float32).tolist()))
+        d[planted] = 1.0
+        qrows.append(d)
+    queries = csr_from_dict_rows(dict(enumerate(qrows)), len(qrows), vocab)
+    idx = sindi.Index(corpus, alpha=1.0, window=10_000, tile=2_000)
+    ref = oracle.build_index(corpus, 10_000)
+    for gamma in (100, 300):
+        cid, csc = map(_np, idx.search_coarse(queries, gamma, cand_cap=1_000))
+        rid, rsc = oracle.precise_search(ref, queries, gamma)
+        assert np.array_equal(cid, rid), gamma
+        # the zero-score documents start right after the planted negatives
+        for r in range(queries.n_rows):
+            z = cid[r][csc[r] == 0]
+            assert z.size and z[0] >= 60 and not np.isin(z, np.arange(60)).any()
+        ids, sc = map(_np, idx.search(queries, gamma, gamma=gamma, cand_cap=1_000))
+        oid, osc = oracle.approx_search(ref, corpus, queries, 1.0, gamma, gamma)
+        check_ranked(ids, sc)
+        check_scores(corpus, queries, ids, sc, rtol=1e-5)
+        assert np.array_equal(ids, oid), gamma
+
+
+def test_every_retry_stage_gives_the_keep_all_result(sindi, small):
+    """A query whose sampled threshold misses is re-run with a threshold over every tile
+    (rank gamma), and, if that overflows the candidate buffer, with none.  Forced here: the
+    documents of the first tile (the only one sampled) score four times higher than the
+    rest, so the sampled threshold keeps fewer than gamma documents for every query; with a
+    buffer of 4,096 the pass over every tile then resolves every query, with a buffer of
+    gamma it overflows and the keep-all pass follows.  The kernel timing counts the passes.
+    Results are bit-identical to keeping every document from the start."""
+    corpus, queries = small
+    vals = corpus.values.copy()
+    first_tile = WINDOW // -(-WINDOW // TILE)  # windows split into equal tiles
+    vals[:corpus.indptr[first_tile]] *= 4.0
+    skewed = synth.Csr(corpus.indptr, corpus.indices, vals, corpus.n_cols)
+    idx = sindi.Index(skewed, alpha=0.5, window=WINDOW, tile=TILE)
+    assert idx.export(raw=True)["tile_doc"][1] == first_tile
+    base_ids, base_sc = map(_np, idx.search(queries, 20, gamma=200, sample_tiles=-1))
+    sindi.profile_enable(True)
+    try:
+        for cap, stages in ((4_096, 2), (200, 3)):
+            sindi.profile_read(reset=True)
+            ids, sc = map(_np, idx.search(queries, 20, gamma=200, sample_tiles=1, cand_cap=cap))
+            prof = sindi.profile_read(reset=True)
+            assert (ids == base_ids).all(), cap
+            assert sc.tobytes() == base_sc.tobytes(), cap
+            # threshold passes: the sampled one and the one over every tile; scoring
+            # passes: one per stage that ran
+            assert prof["accumulate_threshold"][0] == 2, (cap, prof)
+            assert prof["accumulate_score"][0] == stages, (cap, prof)
+    finally:
+        sindi.profile_enable(False)
+
+
+def test_scores_of_passed_document_values(sindi):
+    """score / score_backward with doc_values: the document values passed are scored, not the
+    index's build-time copy (doubling them doubles every score exactly), and the gradients
+    follow them, against the oracle on the changed corpus."""
+    corpus = synth.generate(3_000, 1_500, nnz=("poisson", 40.0), seed=9)
+    queries = synth.generate(12, 1_500, nnz=("poisson", 15.0), seed=9, stream=1)
+    idx = sindi.Index(corpus, alpha=0.5, window=3_000)
+    rng = np.random.default_rng(9)
+    cand = torch.from_numpy(np.stack([rng.choice(3_000, 30, replace=False)
+                                      for _ in range(12)]).astype(np.int64)).cuda()
+    dq = sindi.DeviceCsr.from_host(queries)
+    xv = torch.from_numpy(corpus.values.copy()).cuda()
+    s1 = idx.score(dq, cand)
+    s2 = idx.score(dq, cand, doc_values=2 * xv)
+    assert torch.equal(s2, 2 * s1)
+    new_vals = (corpus.values * rng.uniform(0.5, 1.5, corpus.nnz)).astype(np.float32)
+    changed = synth.Csr(corpus.indptr, corpus.indices, new_vals, corpus.n_cols)
+    s3 = _np(idx.score(dq, cand, doc_values=torch.from_numpy(new_vals).cuda()))
+    c = _np(cand)
+    exact = oracle.pair_scores(changed, queries, np.repeat(np.arange(12), 30), c.reshape(-1))
+    np.testing.assert_allclose(s3.reshape(-1), exact, rtol=1e-5, atol=1e-6)
+    G = rng.standard_normal((12, 30)).astype(np.float32)
+    gq = torch.zeros(queries.nnz, device="cuda")
+    gx = torch.zeros(corpus.nnz, device="cuda")
+    idx.score_backward(dq, cand, torch.from_numpy(G).cuda(), gq, gx,
+                       doc_values=torch.from_numpy(new_vals).cuda())
+    rq, rx = oracle.score_grad(changed, queries, c, G.astype(np.float64))
+    np.testing.assert_allclose(_np(gq), rq, rtol=1e-5, atol=1e-5 * np.abs(rq).max())
+    np.testing.assert_allclose(_np(gx), rx, rtol=1e-5, atol=1e-5 * np.abs(rx).max())
+    # shapes the kernels would index past are refused before any device work
+    E = sindi.SindiError
+    with pytest.raises(E, match="doc_values"):
+        idx.score(dq, cand, doc_values=xv[:-1])
+    with pytest.raises(E, match="cand"):
+        idx.score(dq, cand[:5])
+    with pytest.raises(E, match="cand"):
+        idx.score(dq, cand.int())
+    with pytest.raises(E, match="grad"):
+        idx.score_backward(dq, cand, torch.zeros(12, 29, device="cuda"), gq, gx)
+    with pytest.raises(E, match="grad_query"):
+        idx.score_backward(dq, cand, torch.from_numpy(G).cuda(), gq[:-1], gx)
+    with pytest.raises(E, match="grad_doc"):
+        idx.score_backward(dq, cand, torch.from_numpy(G).cuda(), gq, gx.double())
