@@ -180,6 +180,36 @@ sindi_status sindi_search(const sindi_index *idx, const sindi_csr *queries, int3
                           void *stream);
 
 /*
+ * sindi_search for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same search, results bit for bit those of sindi_search, with every
+ * piece of device scratch (coarse query terms, per-query status, sampled
+ * maxima, candidate lists, rerank pools) carved from one array of 256 MiB
+ * that the library holds on each device it runs on until the process ends.
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine; the caller passes only inputs and outputs.
+ *   queries   device memory only (on_device = 1), of the index's device,
+ *             which must be the current device
+ *   out_ids / out_scores  device buffers as for sindi_search
+ * Limit: the per-query part (20 bytes per query plus 8 per query entry, 16
+ * per entry with beta < 1, each piece rounded up to 256 bytes) and one query
+ * of the largest pass
+ * a retry may need (8 bytes per document of the index for the pass that
+ * keeps every document) must fit the 256 MiB together; otherwise the call
+ * returns SINDI_E_INVALID with the sizes, before any device work, and leaves
+ * the outputs untouched (sindi_search has no such limit).  Queries are
+ * processed in groups that fit the rest of the array.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents; everything that must start at zero is cleared in-stream.  Calls
+ * are synchronous and the library runs one at a time per device (a second
+ * thread's call waits); calls from two processes sharing a device each use
+ * their own process's array.  Blocks until the results are written.
+ */
+sindi_status sindi_search_noalloc(const sindi_index *idx, const sindi_csr *queries, int32_t k,
+                                  const sindi_search_params *params, int64_t *out_ids,
+                                  float *out_scores, void *stream);
+
+/*
  * Alg. 2 (PreciseSindiSearch) over the index: the first k documents by the
  * coarse score (inner product of beta-mass(q) with the pruned documents as
  * stored, FP32 accumulation), no rerank.  Same buffers as sindi_search.

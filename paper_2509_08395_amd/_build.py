@@ -24,7 +24,8 @@ def compile_native(force: bool = True, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src, extra in (("sindi_kernels.hip", DEVICE), ("sindi_build.hip", DEVICE),
-                        ("sindi_host.cpp", DEVICE), ("sindi_server.cpp", DEVICE)):
+                        ("sindi_host.cpp", DEVICE), ("sindi_server.cpp", DEVICE),
+                        ("sindi_noalloc.hip", DEVICE)):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:

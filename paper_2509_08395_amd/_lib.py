@@ -69,7 +69,8 @@ PROFILE_CLASSES = ("query_prep", "accumulate_threshold", "accumulate_score", "th
                    "finalize")
 
 EXPORTS = ("sindi_build", "sindi_index_free", "sindi_index_get_info", "sindi_index_export",
-           "sindi_search", "sindi_search_coarse", "sindi_score_forward", "sindi_score_backward",
+           "sindi_search", "sindi_search_noalloc", "sindi_search_coarse", "sindi_score_forward",
+           "sindi_score_backward",
            "sindi_server_create", "sindi_server_submit", "sindi_server_wait",
            "sindi_server_replay", "sindi_server_get_stats", "sindi_server_destroy",
            "sindi_profile_enable", "sindi_profile_read", "sindi_last_error", "sindi_version")
@@ -104,13 +105,13 @@ def load():
     lib.sindi_index_free.restype = None
     lib.sindi_index_get_info.argtypes = [P, ctypes.POINTER(SindiIndexInfo)]
     lib.sindi_index_export.argtypes = [P, P, P, P, P, P]
-    for f in (lib.sindi_search, lib.sindi_search_coarse):
+    for f in (lib.sindi_search, lib.sindi_search_coarse, lib.sindi_search_noalloc):
         f.argtypes = [P, ctypes.POINTER(SindiCsr), I32, ctypes.POINTER(SindiSearchParams), P, P, P]
     lib.sindi_score_forward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P, P]
     lib.sindi_score_backward.argtypes = [P, ctypes.POINTER(SindiCsr), P, I32, P, P, P, P, P]
     for f in (lib.sindi_build, lib.sindi_index_get_info, lib.sindi_index_export,
-              lib.sindi_search, lib.sindi_search_coarse, lib.sindi_score_forward,
-              lib.sindi_score_backward):
+              lib.sindi_search, lib.sindi_search_coarse, lib.sindi_search_noalloc,
+              lib.sindi_score_forward, lib.sindi_score_backward):
         f.restype = ctypes.c_int
     lib.sindi_server_create.argtypes = [P, ctypes.POINTER(SindiServerParams), ctypes.POINTER(P)]
     lib.sindi_server_submit.argtypes = [P, P, P, I32, I32, ctypes.POINTER(I64)]
