@@ -255,6 +255,21 @@ def test_precise_search_equals_full_sort_with_ties():
             assert sc[q].tolist() == S[q][ids[q]].tolist()
 
 
+def test_precise_search_ranks_every_document_once_with_a_short_last_window():
+    """With k = n_docs Alg. 2 returns each document exactly once: the last window (here 13 of
+    50 documents) is scanned only up to the corpus's end, so no id past it enters the heap, not
+    even ahead of documents whose signed scores fall below zero."""
+    rng = np.random.default_rng(11)
+    corpus = synth.random_csr(rng, 113, 30, 8, signed=True)
+    queries = synth.random_csr(rng, 6, 30, 6, signed=True, min_nnz=1)
+    S = dense(queries) @ dense(corpus).T
+    assert (S < 0).any(axis=1).all()
+    ids, sc = oracle.precise_search(oracle.build_index(corpus, 50), queries, 113)
+    for q in range(6):
+        assert sorted(ids[q].tolist()) == list(range(113))
+        assert ids[q].tolist() == rank_order(S[q]).tolist()
+
+
 def test_coarse_scores_are_per_document_dots_of_pruned_vectors():
     """Summing postings over the query's lists equals each pruned document's dot (Sec. 3.2)."""
     rng = np.random.default_rng(8)
@@ -292,9 +307,15 @@ def test_approx_reduces_to_exact_without_pruning():
     idx = oracle.build_index(corpus, 128)
     ex_ids, ex_sc = oracle.exact_topk(corpus, queries, 10)
     for gamma in (10, 50, 500):
-        ids, sc = oracle.approx_search(idx, corpus, queries, 1.0, gamma, 10)
+        ids, sc, pid, _ = oracle.approx_search(idx, corpus, queries, 1.0, gamma, 10,
+                                               want_pool=True)
         assert ids.tolist() == ex_ids.tolist()
         assert sc.tobytes() == ex_sc.tobytes()
+        # the pool holds real documents only: 500 is not a multiple of the window, and a scan
+        # of the last window past the corpus's end would admit ids 500..511 with coarse score 0,
+        # ahead of the documents whose signed scores are negative
+        assert ((pid >= 0) & (pid < 500)).all()
+    assert all(sorted(row) == list(range(500)) for row in pid.tolist())
 
 
 def test_approx_rerank_scores_are_exact_for_returned_ids():
