@@ -86,7 +86,8 @@ def measured_traffic(config):
     """HBM bytes per scoring launch from the committed rocprofv3 counter summary, if it was
     taken on this kernel code and configuration; else None."""
     src = os.path.join(ROOT, "paper_2509_08395_amd", "csrc", "sindi_kernels.hip")
-    path = os.path.join(ROOT, "profiles", f"k_accumulate1_{config['workload']}_{config['value_storage']}.md")
+    path = os.path.join(ROOT, "profiles",
+                        f"k_accumulate1_queue_{config['workload']}_{config['value_storage']}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -96,7 +97,8 @@ def measured_traffic(config):
             fields[key.strip()] = val.strip()
     sha = kernel_code_sha256(src)
     want = (f"batch={config['batch']} tile={config['tile']} value_storage={config['value_storage']} "
-            f"n_queries={config['n_queries']} n_docs={config['n_docs']}")
+            f"n_queries={config['n_queries']} n_docs={config['n_docs']} alpha={config['alpha']} "
+            f"beta={config['beta']}")
     if fields.get("kernel_code_sha256") != sha or fields.get("config") != want:
         return None
     return int(fields["fetch_bytes_per_launch"]) + int(fields["write_bytes_per_launch"])
@@ -142,12 +144,20 @@ def main():
                          "exact top-k of every query, or 1,000 without it)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the alpha / gamma / beta / storage sweep")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip the second workload shapes and the pruning-rule comparison")
     ap.add_argument("--oracle-queries", type=int, default=7000)
     ap.add_argument("--no-oracle", action="store_true", help="skip recall and the CPU baseline")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="open-loop serving run per arrival rate (0: skip serving)")
     ap.add_argument("--serve-rates", default="",
                     help="comma-separated arrival rates, queries/s (default: the serving workload's)")
+    ap.add_argument("--serve-beta", type=float, default=0.8,
+                    help="query mass ratio of the served searches' coarse stage (Sec. 4.1)")
+    ap.add_argument("--serve-recall-queries", type=int, default=48,
+                    help="serving-shaped queries checked against the exact oracle")
+    ap.add_argument("--serve-inflight", type=int, default=3, help="server batch slots")
+    ap.add_argument("--serve-max-batch", type=int, default=256, help="server batch cap")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP32 / BF16 posting-storage comparison")
     ap.add_argument("--no-diff", action="store_true",
@@ -270,7 +280,8 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": traffic,
         "achieved_is": "HBM bytes beyond L2 per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                        "copy-calibrated, profiles/) over the launch time by HIP events",
-        "kernel": "k_accumulate1 (scoring pass)", "launch_ms": round(acc_ms_avg, 3),
+        "kernel": "k_accumulate1_queue (scoring pass, one persistent launch)",
+        "launch_ms": round(acc_ms_avg, 3),
         "launches_per_step": launches_per_step, "batch": batch,
         "algorithmic_bytes_per_launch": bytes_per_launch,
         "algorithmic_GBs": round(bytes_per_launch / launch_s / 1e9, 1) if launch_s else None,
@@ -308,13 +319,14 @@ def main():
     }
 
     if args.serve_seconds > 0 and dtype == "f16" and wl.name == "splade-8.8m":
-        result["serving"] = serving_leg(sindi, idx, args)
-        result["latency_p99_ms"] = {str(int(r["offered_qps"])): r["p99_ms"]
-                                    for r in result["serving"]["rates"]}
+        optional_leg(result, "serving", lambda: serving_leg(sindi, idx, args, corpus))
+        if "rates" in result["serving"]:
+            result["latency_p99_ms"] = {str(int(r["offered_qps"])): r["p99_ms"]
+                                        for r in result["serving"]["rates"]}
 
     main_leg = wl.name == "splade-8.8m" and dtype == "f16"
     if not args.no_diff and main_leg:
-        result["differentiation"] = diff_leg(sindi)
+        optional_leg(result, "differentiation", lambda: diff_leg(sindi))
 
     if not args.no_oracle:
         import oracle  # CPU baseline, recall and agreement only
@@ -391,13 +403,39 @@ def main():
                             "score_pass_ms": result["kernels_ms_per_step"]["accumulate_score"],
                             "recall_at_k": result["recall_at_k"], "bytes_per_posting": 4,
                             **coarse_error(idx, dqs, qs, pruned, k)}}
-            prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, tsel, truth_t, n_q,
-                                      dqs, qs, pruned))
+            try:
+                prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, tsel, truth_t,
+                                          n_q, dqs, qs, pruned))
+            except Exception as e:  # noqa: BLE001 -- reported in the JSON line
+                log(f"precision leg failed: {type(e).__name__}: {e}")
+                prec["error"] = f"{type(e).__name__}: {e}"
             result["precision"] = prec
+        if not args.no_shapes and main_leg:
+            optional_leg(result, "shapes", lambda: shapes_leg(sindi))
+            # one strength of each pruning rule at about the same kept fraction
+            optional_leg(result, "ablation", lambda: ablation(args, gammas=(10, 30), grid=[
+                ("mrp", dict(alpha=0.5)), ("vnp", dict(vn=22)), ("lp", dict(list_len=20_000)),
+                ("mrp+lp", dict(alpha=0.5, list_len=20_000))]))
         if not args.no_sweep and main_leg:
             idx.close()  # room for the sweep's indexes
-            result["sweep"] = sweep_leg(sindi, corpus, dq, wl, k, tsel, truth_t, rec_note)
+            optional_leg(result, "sweep",
+                         lambda: sweep_leg(sindi, corpus, dq, wl, k, tsel, truth_t, rec_note))
+            best = result["sweep"].get("best_at_recall_0.99", {}).get(dtype)
+            if best:
+                result["qps_best_at_recall_0.99"] = {**best, "note": "fastest sweep point with "
+                                                     "Recall@50 >= 0.99 (value is the configuration "
+                                                     "point: alpha 0.5, gamma 500, beta 1)"}
     print(json.dumps(result), flush=True)
+
+
+def optional_leg(result, name, fn):
+    """Run one secondary leg into result[name]; a failure is logged and recorded there, so the
+    main measurement is never lost to it."""
+    try:
+        result[name] = fn()
+    except Exception as e:  # noqa: BLE001 -- reported in the JSON line
+        log(f"{name} leg failed: {type(e).__name__}: {e}")
+        result[name] = {"error": f"{type(e).__name__}: {e}"}
 
 
 def load_truth(wl, corpus, queries, k):
@@ -549,7 +587,7 @@ def diff_leg(sindi, steps=5):
     return rec
 
 
-def serving_leg(sindi, idx, args):
+def serving_leg(sindi, idx, args, corpus):
     """Open-loop Poisson arrivals at each rate into the continuous-batching server over the
     same index; latency = completion on the host minus scheduled arrival."""
     from synth.workloads import WORKLOADS
@@ -557,21 +595,34 @@ def serving_leg(sindi, idx, args):
     rates = ([float(x) for x in args.serve_rates.split(",")] if args.serve_rates
              else list(wl.extra["rates"]))
     out = []
+    beta = args.serve_beta
     # the GPU's rate on this query mix with no request loop: one search call over 7,000
-    # serving-shaped queries (k = 100), the ceiling the loop's batches approach
+    # serving-shaped queries (k = 100), the ceiling the loop's batches approach, at the
+    # serving beta and at beta 1; and Recall@100 of both against the exact oracle on a sample
+    # (a request served in a batch gets exactly the search of its query alone)
     import torch
-    qb = sindi.DeviceCsr.from_host(wl.queries(7_000, row0=1 << 40))
-    idx.search(qb, 100, gamma=wl.gamma)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        idx.search(qb, 100, gamma=wl.gamma)
-    torch.cuda.synchronize()
-    batch_qps = 3 * 7_000 / (time.perf_counter() - t0)
-    log(f"serving mix, one call of 7,000 queries: {batch_qps:.0f} QPS")
+    import oracle
+    qh = wl.queries(7_000, row0=1 << 40)
+    qb = sindi.DeviceCsr.from_host(qh)
+    ceiling, found = {}, {}
+    for b in sorted({beta, 1.0}):
+        ids, _ = idx.search(qb, 100, beta=b, gamma=wl.gamma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            idx.search(qb, 100, beta=b, gamma=wl.gamma)
+        torch.cuda.synchronize()
+        ceiling[b] = 3 * 7_000 / (time.perf_counter() - t0)
+        found[b] = ids.cpu().numpy()
+    rsel = np.linspace(0, 6_999, args.serve_recall_queries).astype(np.int64)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    truth, _ = oracle.exact_topk(corpus, qh.take_rows(rsel), 100, threads=threads)
+    recall = {b: oracle.recall_at_k(found[b][rsel], truth) for b in found}
+    log(f"serving mix, one call of 7,000 queries: {ceiling} QPS; Recall@100 on {len(rsel)}: {recall}")
     del qb
     row0 = 0
-    with sindi.Server(idx, max_inflight=2, max_batch=512, k_max=100, gamma=wl.gamma) as srv:
+    with sindi.Server(idx, max_inflight=args.serve_inflight, max_batch=args.serve_max_batch,
+                      k_max=100, gamma=wl.gamma, beta=beta) as srv:
         for i, rate in enumerate(rates):
             n = max(1, int(rate * args.serve_seconds))
             q = wl.queries(n, row0=row0)
@@ -590,16 +641,61 @@ def serving_leg(sindi, idx, args):
                    "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
                    "max_ms": round(float(lat_ms.max()), 3),
                    "mean_batch": round(n / max(batches, 1), 1),
-                   "retried": st1["retried"] - st0["retried"]}
+                   "largest_batch": st1["largest_batch"],
+                   "retried": st1["retried"] - st0["retried"],
+                   "memory_waits": st1["memory_waits"] - st0["memory_waits"]}
             log(f"serving {rec}")
             out.append(rec)
     return {"workload": "serving", "query_nnz": "uniform 5..200", "k": "uniform {10, 50, 100}",
-            "batch_call_qps": round(batch_qps, 1),
-            "gamma": wl.gamma, "seconds_per_rate": args.serve_seconds, "max_inflight": 2,
-            "max_batch": 512, "rates": out}
+            "beta": beta,
+            "batch_call_qps": {f"beta={b}": round(v, 1) for b, v in ceiling.items()},
+            "recall_at_100": {f"beta={b}": round(v, 5) for b, v in recall.items()},
+            "recall_sample": f"{len(rsel)} of 7,000 serving-shaped queries, exact FP64 oracle",
+            "gamma": wl.gamma, "seconds_per_rate": args.serve_seconds,
+            "max_inflight": args.serve_inflight, "max_batch": args.serve_max_batch,
+            "arena_peak_bytes": st1["arena_peak_bytes"], "rates": out}
 
 
-def ablation(args, n_docs=1_000_000, n_queries=1_000, gammas=(10, 30, 100), k=10, steps=3):
+def shapes_leg(sindi, steps=3):
+    """The second workload shapes on 1M documents: AntSparse-shaped (vocabulary 250,000, ~40
+    non-zeros per document, ~6 per query, alpha 0.85, lambda 50,000) and RANDOM-shaped
+    (uniform term ids and values, vocabulary 30,000, ~120 / ~50 non-zeros, alpha 0.5), FP16
+    postings, gamma 500, k 50: QPS, and Recall@50 on all 1,000 queries against the exact
+    oracle beside the oracle's own Alg. 4 recall (the method's loss, not the GPU's)."""
+    import torch
+    import oracle
+    from synth.workloads import WORKLOADS
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = []
+    for name in ("antsparse-1m", "random-1m"):
+        wl = WORKLOADS[name]
+        corpus, queries = wl.corpus(), wl.queries()
+        idx = sindi.Index(corpus, alpha=wl.alpha, window=wl.window, value_dtype=wl.value_dtype,
+                          gpu_build=True)
+        dq = sindi.DeviceCsr.from_host(queries)
+        ids, _ = idx.search(dq, wl.k, gamma=wl.gamma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            idx.search(dq, wl.k, gamma=wl.gamma)
+        torch.cuda.synchronize()
+        qps = wl.n_queries * steps / (time.perf_counter() - t0)
+        idx.close()
+        truth, _ = oracle.exact_topk(corpus, queries, wl.k, threads=threads)
+        oidx = oracle.build_index(corpus, wl.window, oracle.mass_prune(corpus, wl.alpha, threads=threads))
+        o_ids, _ = oracle.approx_search(oidx, corpus, queries, wl.beta, wl.gamma, wl.k, threads=threads)
+        rec = {"workload": name, "n_docs": wl.n_docs, "vocab": wl.vocab, "n_queries": wl.n_queries,
+               "alpha": wl.alpha, "qps": round(qps, 1),
+               "recall_at_k": round(oracle.recall_at_k(ids.cpu().numpy(), truth), 5),
+               "oracle_alg4_recall_at_k": round(oracle.recall_at_k(o_ids, truth), 5),
+               "alg4_agreement": round(oracle.recall_at_k(ids.cpu().numpy(), o_ids), 5)}
+        log(f"shape {rec}")
+        out.append(rec)
+    return out
+
+
+def ablation(args, n_docs=1_000_000, n_queries=1_000, gammas=(10, 30, 100), k=10, steps=3,
+             grid=None):
     """The pruning rules of Sec. 4.1 at several strengths on the same corpus and queries,
     each searched with several rerank pools (a pool of k shows the coarse ranking alone)."""
     import torch
@@ -611,10 +707,10 @@ def ablation(args, n_docs=1_000_000, n_queries=1_000, gammas=(10, 30, 100), k=10
     sel = np.linspace(0, n_queries - 1, 200).astype(np.int64)
     truth, _ = oracle.exact_topk(corpus, queries.take_rows(sel), k)
     dq = sindi.DeviceCsr.from_host(queries)
-    grid = ([("mrp", dict(alpha=a)) for a in (0.3, 0.4, 0.5, 0.6, 0.7)] +
-            [("vnp", dict(vn=v)) for v in (8, 14, 22, 30, 45)] +
-            [("lp", dict(list_len=l)) for l in (2_000, 5_000, 10_000, 20_000, 50_000)] +
-            [("mrp+lp", dict(alpha=0.5, list_len=l)) for l in (5_000, 20_000, 50_000)])
+    grid = grid or ([("mrp", dict(alpha=a)) for a in (0.3, 0.4, 0.5, 0.6, 0.7)] +
+                    [("vnp", dict(vn=v)) for v in (8, 14, 22, 30, 45)] +
+                    [("lp", dict(list_len=l)) for l in (2_000, 5_000, 10_000, 20_000, 50_000)] +
+                    [("mrp+lp", dict(alpha=0.5, list_len=l)) for l in (5_000, 20_000, 50_000)])
     rows = []
     for prune, kw in grid:
         idx = sindi.Index(corpus, window=wl.window, value_dtype="f16", prune=prune, **kw)

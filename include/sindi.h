@@ -104,6 +104,11 @@ typedef struct {
     int32_t sample_tiles;    /* tiles scored first to set each query's candidate threshold;
                                 0 -> library default, -1 -> no threshold (keep every doc)    */
     int32_t tile_run;        /* consecutive tiles swept by one workgroup; 0 -> default       */
+    int32_t schedule;        /* scoring launches with one query per workgroup: 1 one
+                                workgroup per (query, tile run); 2 one persistent launch of
+                                the workgroups the device holds at once, each taking (query,
+                                tile run) items from a device queue until it is empty;
+                                0 -> library default.  Results are the same bit for bit.    */
 } sindi_search_params;
 
 /* Summary of a built index. */
@@ -279,7 +284,7 @@ sindi_status sindi_score_backward(const sindi_index *idx, const sindi_csr *queri
  * outputs) for its whole life; the index must outlive the server.
  */
 typedef struct {
-    int32_t max_inflight;     /* batches on the device at once (streams); 0 -> 2, at most 8 */
+    int32_t max_inflight;     /* batches on the device at once (streams); 0 -> 3, at most 8 */
     int32_t max_batch;        /* queries per batch; 0 -> 256, at most 8192                   */
     int32_t k_max;            /* largest k of a request, <= gamma; 0 -> 100                  */
     int32_t max_query_nnz;    /* longest query row accepted; 0 -> 512, at most 4096          */

@@ -209,7 +209,7 @@ class Index:
         return (np.diff(start, axis=1) - (goff[:, :-1] >> 30)).sum(axis=0)
 
     def _run(self, fn, queries, k, beta, gamma, batch, cand_cap, sample_tiles, stream, out,
-             tile_run=0):
+             tile_run=0, schedule=0):
         import torch
         qs, keep = _query_struct(queries)
         nq = qs.n_rows
@@ -219,7 +219,7 @@ class Index:
         else:
             ids, scores = out
         params = _lib.SindiSearchParams(float(beta), int(gamma), int(batch), int(cand_cap),
-                                        int(sample_tiles), int(tile_run))
+                                        int(sample_tiles), int(tile_run), int(schedule))
         _lib.check(fn(self._h, ctypes.byref(qs), int(k), ctypes.byref(params),
                       ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(scores.data_ptr()),
                       _stream(stream)))
@@ -227,16 +227,16 @@ class Index:
         return ids, scores
 
     def search(self, queries, k, beta=1.0, gamma=0, batch=0, cand_cap=0, sample_tiles=0,
-               stream=None, out=None, tile_run=0):
+               stream=None, out=None, tile_run=0, schedule=0):
         """Alg. 4: (ids int64 [n, k], scores float32 [n, k]) as CUDA tensors."""
         return self._run(_lib.load().sindi_search, queries, k, beta, gamma, batch, cand_cap,
-                         sample_tiles, stream, out, tile_run)
+                         sample_tiles, stream, out, tile_run, schedule)
 
     def search_coarse(self, queries, k, beta=1.0, batch=0, cand_cap=0, sample_tiles=0,
-                      stream=None, out=None, tile_run=0):
+                      stream=None, out=None, tile_run=0, schedule=0):
         """Alg. 2 over the (pruned) index: coarse top-k, no rerank."""
         return self._run(_lib.load().sindi_search_coarse, queries, k, beta, 0, batch, cand_cap,
-                         sample_tiles, stream, out, tile_run)
+                         sample_tiles, stream, out, tile_run, schedule)
 
     def _score_args(self, queries, cand, doc_values):
         """Checks the shapes the score kernels index by (they cannot see buffer sizes)."""
@@ -290,12 +290,12 @@ class Server:
     as a stream is free.  Results are host numpy arrays.
     """
 
-    def __init__(self, index, max_inflight=2, max_batch=256, k_max=100, max_query_nnz=512,
+    def __init__(self, index, max_inflight=3, max_batch=256, k_max=100, max_query_nnz=512,
                  max_queue=0, workspace_bytes=0, beta=1.0, gamma=0, batch=0, cand_cap=0,
-                 sample_tiles=0, tile_run=0):
+                 sample_tiles=0, tile_run=0, schedule=0):
         lib = _lib.load()
         sp = _lib.SindiSearchParams(float(beta), int(gamma), int(batch), int(cand_cap),
-                                    int(sample_tiles), int(tile_run))
+                                    int(sample_tiles), int(tile_run), int(schedule))
         params = _lib.SindiServerParams(int(max_inflight), int(max_batch), int(k_max),
                                         int(max_query_nnz), int(max_queue), int(workspace_bytes),
                                         sp)

@@ -34,7 +34,7 @@ PRUNE = {"mrp": 0, "vnp": 1, "lp": 2, "mrp+lp": 3}
 class SindiSearchParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("gamma", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("cand_cap", ctypes.c_int32), ("sample_tiles", ctypes.c_int32),
-                ("tile_run", ctypes.c_int32)]
+                ("tile_run", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
 
 class SindiIndexInfo(ctypes.Structure):

@@ -113,11 +113,14 @@ hipError_t launch_query_prep(const DevQueries &q, int64_t n_cols, double beta, D
                              const float *term_max, double *scratch_abs, int32_t *err_flag,
                              hipStream_t s);
 
+// queue: null launches one workgroup per (slot, tile run); otherwise (one query per
+// workgroup only) one persistent launch of the device's resident workgroups takes the items
+// from the 8-byte counter *queue, which must be zero when the launch starts.
 hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                              int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
                              int32_t n_sample_tiles, float *maxima, const float *theta,
                              uint32_t *count, uint64_t *cand, int64_t cap, int32_t tiles_per_wg,
-                             int32_t max_terms, hipStream_t s);
+                             int32_t max_terms, unsigned long long *queue, hipStream_t s);
 
 hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,
                         float *theta, hipStream_t s);

@@ -23,8 +23,10 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <utility>
 
@@ -859,11 +861,15 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 // The first segment's terms, weights and list bounds (the next tile's
 // prefetched during the current one) stay in registers; further segments
 // are reloaded (cache hits) where used.
+//
+// One work item: query slot `slot` over tile run `run` (tiles [run R, (run + 1) R)).  The
+// score row must be all zero on entry unless clear_row (the read-out of every tile clears what
+// the tile's adds touched, so it is all zero again on return).
 template <int VT, bool SAMPLE>
-__global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_accumulate1(
-    DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
+__device__ __forceinline__ void accumulate1_item(
+    const DevIndex &ix, const DevQueries &q, const DevCoarse &c, const int32_t *slot_q,
     int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
-    int64_t cap, int32_t tiles_per_wg)
+    int64_t cap, int32_t tiles_per_wg, int32_t slot, int64_t run, bool clear_row)
 {
     constexpr int NT = kAccThreads, NW = NT / kWave;
     constexpr int KU = VT == 0 ? 4 : 8;  // chunks in flight per wave
@@ -871,7 +877,6 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     int32_t *A32 = reinterpret_cast<int32_t *>(smem);  // the query's score row [tile_stride]
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wave = (int)uni((uint32_t)tid / kWave);
-    const int32_t slot = blockIdx.x;  // one workgroup per query slot: slot < n_slots
     const int32_t row = slot_q[slot];
     const int64_t qa = q.indptr[row];
     const int32_t n = c.cn[row];
@@ -890,13 +895,13 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
     const float w0 = lane < n ? c.cw[qa + lane] : 0.0f;
     using Raw = typename Val<VT>::Raw;
     const int64_t n_tile_iter = SAMPLE ? n_sample : ix.n_tiles;
-    const int64_t ti_beg = (int64_t)blockIdx.y * tiles_per_wg;
+    const int64_t ti_beg = run * tiles_per_wg;
     const int64_t ti_end = min(n_tile_iter, ti_beg + tiles_per_wg);
     const size_t toff_stride = (size_t)(ix.n_cols + 1);
     auto tile_of = [&](int64_t ti) { return SAMPLE ? (ti * ix.n_tiles / n_sample) : ti; };
 
     // the score row starts cleared; reading a tile's row clears it again
-    {
+    if (clear_row) {
         int4 *A4 = reinterpret_cast<int4 *>(smem);
         for (int i = tid; i < ix.tile_stride / 4; i += NT) A4[i] = make_int4(0, 0, 0, 0);
     }
@@ -1097,6 +1102,45 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))
                 read_out(std::false_type{});
         }
         __syncthreads();
+    }
+}
+
+// One workgroup per (query slot, tile run): grid (slots, runs), slots fastest, so the
+// workgroups resident together score the same tiles.
+template <int VT, bool SAMPLE>
+__global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_accumulate1(
+    DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
+    int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
+    int64_t cap, int32_t tiles_per_wg)
+{
+    (void)n_slots;
+    accumulate1_item<VT, SAMPLE>(ix, q, c, slot_q, n_sample, maxima, theta, count, cand, cap,
+                                 tiles_per_wg, (int32_t)blockIdx.x, (int64_t)blockIdx.y, true);
+}
+
+// The same work as one persistent launch fed by a device work queue: as many workgroups as
+// the device holds at once, each taking the next (slot, tile run) item from a counter until
+// the queue is empty.  Items run in the grid's order (tile run major, slots in order), so the
+// workgroups resident together still score the same tiles, and a caller that orders its
+// slots by decreasing work starts the long queries of each run first.  Every workgroup leaves
+// once the counter passes the last item; *head must be 0 at launch.
+template <int VT, bool SAMPLE>
+__global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_accumulate1_queue(
+    DevIndex ix, DevQueries q, DevCoarse c, const int32_t *slot_q, int32_t n_slots,
+    int32_t n_sample, float *maxima, const float *theta, uint32_t *count, uint64_t *cand,
+    int64_t cap, int32_t tiles_per_wg, int64_t n_items, unsigned long long *head)
+{
+    __shared__ int64_t s_item;
+    bool first = true;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(head, 1ull);
+        __syncthreads();
+        const int64_t it = s_item;
+        __syncthreads();  // every thread has the item before thread 0 takes the next
+        if (it >= n_items) break;
+        accumulate1_item<VT, SAMPLE>(ix, q, c, slot_q, n_sample, maxima, theta, count, cand, cap,
+                                     tiles_per_wg, (int32_t)(it % n_slots), it / n_slots, first);
+        first = false;
     }
 }
 
@@ -1562,11 +1606,37 @@ hipError_t set_lds(F *kernel, size_t bytes)
     return allow_lds(reinterpret_cast<const void *>(kernel), bytes);
 }
 
+// Workgroups of `kernel` (kAccThreads threads, `lds` bytes of dynamic LDS) the device holds
+// at once, looked up once per (device, kernel, lds).
+template <typename F>
+hipError_t resident_workgroups(F *kernel, size_t lds, int64_t *out)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, size_t>, int64_t> known;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(dev, reinterpret_cast<const void *>(kernel), lds);
+    auto it = known.find(key);
+    if (it == known.end()) {
+        int per_cu = 0, cus = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kAccThreads, lds)) != hipSuccess)
+            return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return e;
+        it = known.emplace(key, std::max<int64_t>(1, (int64_t)per_cu * cus)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
 template <int VT, int B, bool SAMPLE>
 hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                           const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
                           const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
-                          int32_t tiles_per_wg, int32_t max_terms, hipStream_t s)
+                          int32_t tiles_per_wg, int32_t max_terms, unsigned long long *queue,
+                          hipStream_t s)
 {
     const int eb = entry_block(B, max_terms);
     const size_t lds = accumulate_lds_bytes(B, ix.tile_stride, eb);
@@ -1590,6 +1660,17 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
     }
     dim3 grid((unsigned)n_batches, (unsigned)groups);
     if constexpr (B == 1) {
+        if (queue) {  // one persistent launch over the (slot, run) items
+            if ((e = set_lds(k_accumulate1_queue<VT, SAMPLE>, lds)) != hipSuccess) return e;
+            int64_t wgs = 0;
+            if ((e = resident_workgroups(k_accumulate1_queue<VT, SAMPLE>, lds, &wgs)) != hipSuccess)
+                return e;
+            const int64_t n_items = n_batches * groups;
+            hipLaunchKernelGGL((k_accumulate1_queue<VT, SAMPLE>), dim3((unsigned)std::min(wgs, n_items)),
+                               dim3(kAccThreads), lds, s, ix, q, c, slot_q, n_slots, n_sample,
+                               maxima, theta, count, cand, cap, (int32_t)per, n_items, queue);
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL((k_accumulate1<VT, SAMPLE>), grid, dim3(kAccThreads), lds, s, ix, q, c,
                            slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, (int32_t)per);
     } else {
@@ -1604,13 +1685,14 @@ template <int VT, bool SAMPLE>
 hipError_t dispatch_b(int batch, const DevIndex &ix, const DevQueries &q, const DevCoarse &c,
                       const int32_t *slot_q, int32_t n_slots, int32_t n_sample, float *maxima,
                       const float *theta, uint32_t *count, uint64_t *cand, int64_t cap,
-                      int32_t tiles_per_wg, int32_t max_terms, hipStream_t s)
+                      int32_t tiles_per_wg, int32_t max_terms, unsigned long long *queue,
+                      hipStream_t s)
 {
     switch (batch) {
-    case 1: return run_accumulate<VT, 1, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
-    case 2: return run_accumulate<VT, 2, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
-    case 4: return run_accumulate<VT, 4, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
-    case 8: return run_accumulate<VT, 8, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+    case 1: return run_accumulate<VT, 1, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, queue, s);
+    case 2: return run_accumulate<VT, 2, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, nullptr, s);
+    case 4: return run_accumulate<VT, 4, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, nullptr, s);
+    case 8: return run_accumulate<VT, 8, SAMPLE>(ix, q, c, slot_q, n_slots, n_sample, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, nullptr, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1656,18 +1738,18 @@ hipError_t launch_accumulate(const DevIndex &ix, const DevQueries &q, const DevC
                              int batch, bool sample, const int32_t *slot_q, int32_t n_slots,
                              int32_t n_sample_tiles, float *maxima, const float *theta,
                              uint32_t *count, uint64_t *cand, int64_t cap, int32_t tiles_per_wg,
-                             int32_t max_terms, hipStream_t s)
+                             int32_t max_terms, unsigned long long *queue, hipStream_t s)
 {
     if (n_slots == 0 || ix.n_tiles == 0) return hipSuccess;
     const int vt = ix.value_dtype;
     if (sample) {
-        if (vt == 0) return dispatch_b<0, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
-        if (vt == 1) return dispatch_b<1, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
-        return dispatch_b<2, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+        if (vt == 0) return dispatch_b<0, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, queue, s);
+        if (vt == 1) return dispatch_b<1, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, queue, s);
+        return dispatch_b<2, true>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, queue, s);
     }
-    if (vt == 0) return dispatch_b<0, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
-    if (vt == 1) return dispatch_b<1, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
-    return dispatch_b<2, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, s);
+    if (vt == 0) return dispatch_b<0, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, queue, s);
+    if (vt == 1) return dispatch_b<1, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, queue, s);
+    return dispatch_b<2, false>(batch, ix, q, c, slot_q, n_slots, n_sample_tiles, maxima, theta, count, cand, cap, tiles_per_wg, max_terms, queue, s);
 }
 
 hipError_t launch_theta(const float *maxima, int64_t n_maxima, int64_t rank, int32_t n_slots,

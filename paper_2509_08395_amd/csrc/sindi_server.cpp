@@ -7,6 +7,7 @@
 // and the host never waits on one batch to start the next.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -222,6 +223,10 @@ sindi_status check_row(const sindi_server *srv, const int32_t *idx, const float 
 // completion event.
 bool sindi_server::launch(Slot &s, std::vector<Request *> &batch)
 {
+    // longest queries first: the scoring passes take (query, tile run) items in slot order,
+    // so each run starts with its longest work (results do not depend on the order)
+    std::stable_sort(batch.begin(), batch.end(),
+                     [](const Request *a, const Request *b) { return a->nnz > b->nnz; });
     const int32_t nb = (int32_t)batch.size();
     int32_t kb = 1, longest = 0;
     int64_t nnz = 0;
@@ -474,7 +479,7 @@ sindi_status create_impl(const sindi_index *ix, const sindi_server_params *pp, s
     if (!ix || !out) return fail(SINDI_E_INVALID, "sindi_server_create: null argument");
     sindi_server_params p{};
     if (pp) p = *pp;
-    if (!p.max_inflight) p.max_inflight = 2;
+    if (!p.max_inflight) p.max_inflight = 3;
     if (!p.max_batch) p.max_batch = 256;
     if (!p.k_max) p.k_max = 100;
     if (!p.max_query_nnz) p.max_query_nnz = 512;

@@ -83,6 +83,7 @@ struct DBuf {
 // The parameters of one search, resolved against the index.
 struct Plan {
     int32_t k = 0, gamma = 0, need = 0, batch = 1, n_sample = 0, tile_run = 0;
+    bool queue = false;    // scoring passes as one persistent, queue-fed launch
     int32_t max_qnnz = 0;  // bound on every query row's length (rerank table size)
     int64_t cap = 0, rank = 0;
     bool keep_all = true, rerank = true;

@@ -8,7 +8,7 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNELS = os.path.join(ROOT, "paper_2509_08395_amd", "csrc", "sindi_kernels.hip")
 DEFAULT = {"workload": "splade-8.8m", "value_storage": "f16", "batch": 1, "tile": 12500,
-           "n_queries": 7000, "n_docs": 8800000}
+           "n_queries": 7000, "n_docs": 8800000, "alpha": 0.5, "beta": 1.0}
 
 
 def test_code_hash_ignores_comments_and_layout_only(tmp_path):
@@ -32,7 +32,8 @@ def test_committed_counter_summary_matches_the_kernel_code():
 
 
 def test_counter_summary_is_not_used_for_another_configuration():
-    for key, val in (("tile", 10000), ("batch", 2), ("n_queries", 1000), ("value_storage", "f32")):
+    for key, val in (("tile", 10000), ("batch", 2), ("n_queries", 1000), ("value_storage", "f32"),
+                     ("alpha", 0.3), ("beta", 0.8)):
         cfg = dict(DEFAULT, **{key: val})
         assert bench.measured_traffic(cfg) is None, key
 

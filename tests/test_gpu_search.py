@@ -585,3 +585,18 @@ def test_scores_of_passed_document_values(sindi):
         idx.score_backward(dq, cand, torch.from_numpy(G).cuda(), gq[:-1], gx)
     with pytest.raises(E, match="grad_doc"):
         idx.score_backward(dq, cand, torch.from_numpy(G).cuda(), gq, gx.double())
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(sample_tiles=1, cand_cap=200),
+                                dict(sample_tiles=-1), dict(tile_run=1), dict(tile_run=65)])
+def test_persistent_queue_schedule_is_bit_identical(sindi, small, kw):
+    """The scoring passes as one persistent launch fed by a device work queue (schedule 2)
+    give exactly the results of one workgroup per (query, tile run) (schedule 1): the same
+    items run, in any order, and integer sums do not depend on it.  Also with every retry
+    stage forced, with no threshold, and with runs of 1 and of more than 64 tiles."""
+    corpus, queries = small
+    idx = sindi.Index(corpus, alpha=0.5, window=WINDOW, tile=TILE)
+    for fn, k, extra in ((idx.search, 20, dict(gamma=200)), (idx.search_coarse, 30, dict())):
+        a_ids, a_sc = map(_np, fn(queries, k, schedule=1, **extra, **kw))
+        b_ids, b_sc = map(_np, fn(queries, k, schedule=2, **extra, **kw))
+        assert (a_ids == b_ids).all() and a_sc.tobytes() == b_sc.tobytes()
