@@ -4,16 +4,18 @@
 //
 //   k_check_rows     structure of a device corpus (Def. 1)
 //   k_prune_rows     MRP (Defs. 5-6) or VNP (Sec. 4.1), one wave per row of up
-//                    to kWaveRow entries; longer rows are listed for
+//                    to kWaveRow entries sorted in registers (bitonic); longer
+//                    rows are listed for
 //   k_prune_long     the same, one workgroup per row of up to kLongRow entries
 //   k_count_lists    entries per (tile, term) list (one workgroup per tile,
 //                    counters in LDS), the storage range check and each
 //                    term's largest stored |x|
 //   k_list_offsets   per tile: 4-posting group offsets of the lists, pad counts
-//   k_fill_lists     one wave per (tile, term pass) streams the tile's entries
-//                    in order and places every kept entry of its terms at its
-//                    list's cursor (LDS), so a list holds its documents in
-//                    ascending order
+//   k_fill_lists     one workgroup per (tile, term pass) places the tile's
+//                    kept entries of its terms, 16 documents at a time, each
+//                    at its list's next slot plus its rank among the batch's
+//                    documents holding the term (LDS), so a list holds its
+//                    documents in ascending order
 //   k_fill_pads      the pad entries after every list
 #include <hip/hip_runtime.h>
 
@@ -32,7 +34,10 @@ constexpr int kWaveRow = 512;     // longest row pruned by one wave
 constexpr int kRowsPerWg = 4;     // waves (rows) per workgroup of k_prune_rows
 constexpr int kCountThreads = 1024;  // k_count_lists workgroup
 constexpr int kCountTerms = 32768;   // 16-bit list counters per pass of k_count_lists (64 KB)
-constexpr int kFillRing = 8;         // chunks of 64 entries in flight per k_fill_lists wave
+constexpr int kFillThreads = 1024;   // k_fill_lists workgroup
+constexpr int kFillDocs = 16;        // documents placed together by k_fill_lists (one bit each)
+constexpr int kFillPer = 4;          // entries per thread and batch of k_fill_lists
+constexpr int64_t kFillCap = (int64_t)kFillThreads * kFillPer;  // entries per batch
 
 // Waits for this wave's LDS operations so that every lane sees the others'.
 __device__ __forceinline__ void wave_sync()
@@ -123,36 +128,186 @@ __device__ __forceinline__ uint64_t order_key(float ax, int32_t id)
     return ax > 0.0f ? ((uint64_t)__float_as_uint(ax) << 32) | (uint32_t)~id : 0ull;
 }
 
-// Ranks of a wave's row held in registers (key of entry i * 64 + lane in slot
-// i of the lane, NC slots in use): for each slot, the number of the row's
-// entries with a larger key, taking the keys one at a time by lane broadcast.
-template <int NC, int PER>
-__device__ __forceinline__ void rank_entries(const uint64_t (&key)[PER], int32_t (&rank)[PER])
+// The value of lane (lane ^ X) for X < 64, all lanes active: quad permutations
+// for 1 and 2, a quad mirror then a half-row mirror for 4 (lane ^ 3 ^ 7), a
+// half-row rotation for 8 (DPP, no LDS traffic); a permute through the LDS
+// crossbar for 16 and 32.
+template <int X>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v)
 {
+    const int x = (int)v;
+    if constexpr (X == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+    else if constexpr (X == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+    else if constexpr (X == 4)
+        return (uint32_t)__builtin_amdgcn_update_dpp(
+            0, __builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false), 0x141, 0xF, 0xF, false);
+    else if constexpr (X == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+    else return (uint32_t)__shfl_xor(x, X, kWave);
+}
+
+template <int X>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v)
+{
+    return ((uint64_t)lane_xor<X>((uint32_t)(v >> 32)) << 32) | lane_xor<X>((uint32_t)v);
+}
+
+// One merge step (blocks of K, distance J) of a bitonic sort of the N = 64 S
+// keys a wave holds, element i = lane * S + s in slot s of the lane: elements
+// i and i ^ J are compared in registers for J < S and across lanes otherwise;
+// the lower element of a pair takes the larger key where i & K is 0 and the
+// smaller elsewhere, so the last merge (K = N) leaves the keys in descending
+// order.  Equal keys are interchangeable.
+template <int S, int K, int J>
+__device__ __forceinline__ void bitonic_step(uint64_t (&key)[S], int lane)
+{
+    if constexpr (J < S) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) rank[i] = 0;
+        for (int s = 0; s < S; ++s) {
+            if (s & J) continue;  // s is the pair's lower slot
+            const bool larger_low = (((lane * S) | s) & K) == 0;
+            const uint64_t a = key[s], b = key[s | J];
+            const bool a_first = (a > b) == larger_low;
+            key[s] = a_first ? a : b;
+            key[s | J] = a_first ? b : a;
+        }
+    } else {
+        constexpr int X = J / S;  // partner lane: lane ^ X
+        const bool take_max = ((lane & X) == 0) == (((lane * S) & K) == 0);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const uint32_t lo = (uint32_t)key[c], hi = (uint32_t)(key[c] >> 32);
-        for (int l = 0; l < kWave; ++l) {
-            const uint64_t f = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, l) << 32) |
-                               (uint32_t)__builtin_amdgcn_readlane((int)lo, l);
-#pragma unroll
-            for (int i = 0; i < NC; ++i) rank[i] += f > key[i] ? 1 : 0;
+        for (int s = 0; s < S; ++s) {
+            const uint64_t a = key[s], p = lane_xor64<X>(a);
+            key[s] = (a > p) == take_max ? a : p;
         }
     }
 }
 
+template <int S, int K, int J>
+__device__ __forceinline__ void bitonic_merge(uint64_t (&key)[S], int lane)
+{
+    bitonic_step<S, K, J>(key, lane);
+    if constexpr (J > 1) bitonic_merge<S, K, J / 2>(key, lane);
+}
+
+template <int S, int K = 2>
+__device__ __forceinline__ void bitonic_desc(uint64_t (&key)[S], int lane)
+{
+    bitonic_merge<S, K, K / 2>(key, lane);
+    if constexpr (K < S * kWave) bitonic_desc<S, K * 2>(key, lane);
+}
+
+// Key of rank r (0 <= r < 64 S) of keys sorted by bitonic_desc, in every lane.
+template <int S>
+__device__ __forceinline__ uint64_t key_at(const uint64_t (&key)[S], int32_t r)
+{
+    uint64_t v = key[0];
+#pragma unroll
+    for (int s = 1; s < S; ++s)
+        if (r % S == s) v = key[s];
+    const int l = r / S;
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+
+// FP64 lane shifted down by D within rows of 16 lanes (0.0 shifted in).
+template <int D>
+__device__ __forceinline__ double row_shr(double v)
+{
+    const uint64_t b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x110 + D, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x110 + D, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Alg. 3 on one row of m entries (n slots read) held by a wave, S slots per
+// lane: the keys sorted in Def. 6 order give every entry's rank, and the row
+// keeps the entries of rank below keep_n, i.e. the keys at or above the key of
+// rank keep_n - 1.  MRP's keep_n comes from the prefix sums of |x| in that
+// order, taken in FP64 one after another (mass_prefix, as the host does), or,
+// where the row's values make every such sum exact, by a scan: all |x| are
+// integer multiples of the smallest one's unit in the last place, u, and when
+// m times the largest stays below 2^53 u no partial sum, in any order of
+// addition, is rounded, so the scan's sums are the sequential ones.
+template <int S>
+__device__ __forceinline__ void prune_row(const int32_t *ridx, const float *rval, int64_t n,
+                                          int32_t mode, double alpha, int32_t vn, uint8_t *rkeep,
+                                          double *s_sum)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t key[S], orig[S];
+    int32_t m = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {  // entry s * 64 + lane; a sort needs no particular start
+        const int64_t e = s * kWave + lane;
+        float ax = -1.0f;
+        int32_t id = 0;
+        if (e < n) {
+            const float v = rval[e];
+            ax = v != 0.0f ? fabsf(v) : -1.0f;  // zeros are not entries (Def. 1)
+            id = ridx[e];
+        }
+        key[s] = orig[s] = order_key(ax, id);
+        m += __popcll(__ballot(ax >= 0.0f));
+    }
+    bitonic_desc<S>(key, lane);  // rank lane * S + s in slot s
+    int32_t keep_n = m;
+    if (mode == SINDI_PRUNE_VNP) {
+        keep_n = min(vn, m);
+    } else if (alpha < 1.0 && m > 0) {
+        const int e_max = max((int)(key_at<S>(key, 0) >> 55), 1);
+        const int e_min = max((int)(key_at<S>(key, m - 1) >> 55), 1);
+        const int lg = m > 1 ? 32 - __clz(m - 1) : 0;  // ceil(log2 m)
+        if (e_max - e_min + lg <= 29) {
+            double pre[S];
+            double run = 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {  // the lane's own ranks
+                run += key[s] ? (double)__uint_as_float((uint32_t)(key[s] >> 32)) : 0.0;
+                pre[s] = run;
+            }
+            // lanes' totals: inclusive scan in rows of 16, then the rows below
+            double x = run;
+            x += row_shr<1>(x);
+            x += row_shr<2>(x);
+            x += row_shr<4>(x);
+            x += row_shr<8>(x);
+            const double r0 = __shfl(x, 15, kWave), r1 = __shfl(x, 31, kWave), r2 = __shfl(x, 47, kWave);
+            x += (lane >= 16 ? r0 : 0.0) + (lane >= 32 ? r1 : 0.0) + (lane >= 48 ? r2 : 0.0);
+            const double before = x - run;  // exact: the lanes below this one
+            const double mass = __shfl(x, kWave - 1, kWave);
+            const double thr = alpha * mass;
+            int first = S;  // the lane's first rank reaching thr
+#pragma unroll
+            for (int s = S - 1; s >= 0; --s)
+                if (before + pre[s] >= thr && lane * S + s < m) first = s;
+            const uint64_t hit = __ballot(first < S);
+            if (hit) {
+                const int l = __ffsll((long long)hit) - 1;
+                keep_n = l * S + __builtin_amdgcn_readlane(first, l) + 1;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (lane * S + s < m) s_sum[lane * S + s] = (double)__uint_as_float((uint32_t)(key[s] >> 32));
+            wave_sync();
+            keep_n = (int32_t)mass_prefix(s_sum, m, alpha);  // the same value in every lane
+        }
+    }
+    const uint64_t kth = keep_n > 0 ? key_at<S>(key, keep_n - 1) : ~0ull;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int64_t e = s * kWave + lane;
+        if (e < n) rkeep[e] = orig[s] != 0ull && orig[s] >= kth ? 1 : 0;
+    }
+}
+
 // One wave per row of at most kWaveRow entries, held in registers (entry
-// i * 64 + lane in slot i of the lane).  Each lane ranks its entries by
-// counting the row's entries before them in Def. 6 order (rank_entries); MRP
-// places |x| at its rank (FP64, in LDS) and the prefix sums run in that order.  Longer rows are appended to
-// long_rows (err bit 128: a row longer than kLongRow).
+// s * 64 + lane in slot s of the lane; slots in use rounded up to a power of
+// two).  Longer rows are appended to long_rows (err bit 128: a row longer than
+// kLongRow).
 __global__ __launch_bounds__(kRowsPerWg * kWave) void k_prune_rows(
     const int64_t *ptr, const int32_t *idx, const float *val, int64_t n_rows, int32_t mode,
     double alpha, int32_t vn, uint8_t *keep, int32_t *long_rows, uint32_t *n_long, int32_t *err)
 {
-    constexpr int PER = kWaveRow / kWave;
     __shared__ double s_sum[kRowsPerWg][kWaveRow];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + w;
@@ -165,53 +320,13 @@ __global__ __launch_bounds__(kRowsPerWg * kWave) void k_prune_rows(
         }
         return;
     }
-    // non-entries (zeros, slots past the row) carry |x| = -1 and key 0
-    float ax[PER];
-    uint64_t key[PER];
-    int32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int64_t e = i * kWave + lane;
-        ax[i] = -1.0f;
-        int32_t id = 0;
-        if (e < n) {
-            const float v = val[a + e];
-            ax[i] = v != 0.0f ? fabsf(v) : -1.0f;  // zeros are not entries (Def. 1)
-            id = idx[a + e];
-        }
-        key[i] = order_key(ax[i], id);
-        m += __popcll(__ballot(ax[i] >= 0.0f));
-    }
-    int32_t rank[PER];
-    switch ((n + kWave - 1) / kWave) {  // slots in use (wave-uniform)
-    case 0: break;
-    case 1: rank_entries<1>(key, rank); break;
-    case 2: rank_entries<2>(key, rank); break;
-    case 3: rank_entries<3>(key, rank); break;
-    case 4: rank_entries<4>(key, rank); break;
-    case 5: rank_entries<5>(key, rank); break;
-    case 6: rank_entries<6>(key, rank); break;
-    case 7: rank_entries<7>(key, rank); break;
-    default: rank_entries<8>(key, rank); break;
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-        if (ax[i] < 0.0f) rank[i] = INT32_MAX;
-    int64_t keep_n;
-    if (mode == SINDI_PRUNE_VNP) {
-        keep_n = min((int64_t)vn, (int64_t)m);
-    } else {
-#pragma unroll
-        for (int i = 0; i < PER; ++i)
-            if (ax[i] >= 0.0f) s_sum[w][rank[i]] = (double)ax[i];
-        wave_sync();
-        keep_n = mass_prefix(s_sum[w], m, alpha);  // the same value in every lane
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int64_t e = i * kWave + lane;
-        if (e < n) keep[a + e] = rank[i] < keep_n ? 1 : 0;
-    }
+    const int32_t *ri = idx + a;
+    const float *rv = val + a;
+    uint8_t *rk = keep + a;
+    if (n <= kWave) prune_row<1>(ri, rv, n, mode, alpha, vn, rk, s_sum[w]);
+    else if (n <= 2 * kWave) prune_row<2>(ri, rv, n, mode, alpha, vn, rk, s_sum[w]);
+    else if (n <= 4 * kWave) prune_row<4>(ri, rv, n, mode, alpha, vn, rk, s_sum[w]);
+    else prune_row<8>(ri, rv, n, mode, alpha, vn, rk, s_sum[w]);
 }
 
 // One workgroup per long row (at most kLongRow entries), staged in LDS: the
@@ -365,82 +480,132 @@ __global__ __launch_bounds__(256) void k_list_offsets(const uint32_t *cnt, int64
     }
 }
 
-// One wave per (tile, pass of pass_terms terms).  The tile's entries are
-// contiguous in the corpus; the wave streams them in chunks of 64 (one per
-// lane), with kFillRing chunks' loads in flight.  The lanes of a chunk belong
-// to consecutive documents (found from the row pointers, wave-uniform scalar
-// loads); the chunk is placed one document at a time, each kept entry of the
-// pass's terms taking its list's next slot by an LDS atomic.  A document's
-// terms are distinct and one wave's LDS operations complete in order, so every
-// list receives its documents in ascending order.
-__global__ __launch_bounds__(kWave) void k_fill_lists(
+// One workgroup per (tile, pass of pass_terms terms) places the tile's kept
+// entries of the pass's terms in their lists, each list holding its documents
+// in ascending order (Alg. 1).  The documents are taken in batches: up to
+// kFillDocs whole documents of at most kFillCap entries together, or a longer
+// document alone, kFillCap entries at a time.  One LDS word per term holds the
+// list's next slot (low 16 bits, from the list's start: a list of a tile holds
+// at most kTileMax < 2^16 entries) and, while a batch is placed, one bit per
+// document of the batch that holds the term (high 16 bits).  Per batch: every
+// kept entry adds its document's bit; after a barrier it takes the slot the
+// word gives plus the number of the batch's earlier documents holding the
+// term; the entry of the last such document then adds to the word the count
+// less the bits, which leaves the next slot with no bits set.  A document holds
+// a term at most once, so a list's slots follow its documents' order, as in a
+// one-document-at-a-time placement.  Additions commute, so each batch's slot
+// advances go with the next batch's bits, two barriers per batch.  The next
+// batch's entries (at most kFillCap from its first) and their lists' offsets
+// are loaded while the current batch is placed.
+__global__ __launch_bounds__(kFillThreads) void k_fill_lists(
     const int64_t *ptr, const int32_t *idx, const float *val, const uint8_t *keep,
     const int64_t *tile_doc, const int64_t *tile_post, const uint32_t *goff, int64_t n_cols,
     int32_t dtype, int32_t pass_terms, uint16_t *post_doc, void *post_val)
 {
-    constexpr int R = kFillRing;
+    constexpr int P = kFillPer;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *cur = reinterpret_cast<uint32_t *>(smem);  // [pass_terms] next slot of each list
-    const int lane = threadIdx.x;
+    uint32_t *word = reinterpret_cast<uint32_t *>(smem);  // [pass_terms]
+    __shared__ int64_t s_bnd[2][kFillDocs + 1];           // first entries of the batch's documents
+    const int tid = threadIdx.x;
     const int64_t t = blockIdx.x;
     const int64_t j0 = (int64_t)blockIdx.y * pass_terms;
     const int64_t j1 = min(n_cols, j0 + pass_terms);
-    if (j0 >= n_cols) return;
+    if (j0 >= n_cols) return;  // the whole workgroup
     const uint32_t *g = goff + (size_t)t * (size_t)(n_cols + 1);
-    for (int64_t j = j0 + lane; j < j1; j += kWave) cur[j - j0] = 4u * (g[j] & kGoffMask);
-    wave_sync();
+    for (int64_t j = tid; j < j1 - j0; j += kFillThreads) word[j] = 0u;
     const int64_t d0 = tile_doc[t], d1 = tile_doc[t + 1], P0 = tile_post[t];
-    const int64_t e0 = ptr[d0], e1 = ptr[d1];
-    int32_t rj[R];
-    uint32_t rk[R];
-    float rv[R];
-    auto fetch = [&](int64_t c, int u) {  // chunk starting at entry c into ring slot u
-        const int64_t e = c + lane;
-        rj[u] = -1;
-        rk[u] = 0u;
-        rv[u] = 0.0f;
-        if (e < e1) {
-            rj[u] = idx[e];
-            rk[u] = keep[e];
-            rv[u] = val[e];
+    const int64_t e1 = ptr[d1];
+    int64_t d = d0, e = ptr[d0];
+    int buf = 0;
+    if (tid <= kFillDocs) s_bnd[0][tid] = ptr[min(d + tid, d1)];
+    int32_t rj[P], nj[P];  // this batch's entries, and the next batch's (in flight)
+    uint32_t rk[P], nk[P];
+    float rv[P], nv[P];
+    uint32_t go[P];                  // list offsets of this batch's entries
+    int32_t up_j[P];                 // a slot advance of the last batch: term (or -1) ...
+    uint32_t up_d[P];                // ... and the amount added to its word
+    auto fetch = [&](int64_t from, int32_t (&fj)[P], uint32_t (&fk)[P], float (&fv)[P]) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int64_t x = from + tid + (int64_t)u * kFillThreads;
+            fj[u] = -1;
+            fk[u] = 0u;
+            fv[u] = 0.0f;
+            if (x < e1) {
+                fj[u] = idx[x];
+                fk[u] = keep[x];
+                fv[u] = val[x];
+            }
         }
     };
+    // list offsets of the entries fetched (some past their batch's end: unused)
+    auto offsets = [&](const int32_t (&fj)[P], const uint32_t (&fk)[P]) {
 #pragma unroll
-    for (int u = 0; u < R; ++u) fetch(e0 + (int64_t)u * kWave, u);
-    int64_t dcur = d0;  // document of the current chunk's first entry
-    for (int64_t c0 = e0; c0 < e1; c0 += (int64_t)R * kWave) {
+        for (int u = 0; u < P; ++u) go[u] = fk[u] != 0u && fj[u] >= j0 && fj[u] < j1 ? g[fj[u]] : 0u;
+    };
+    fetch(e, rj, rk, rv);
+    offsets(rj, rk);
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-            const int64_t c = c0 + (int64_t)u * kWave;
-            if (c < e1) {  // wave-uniform
-                const int64_t e = c + lane, cend = min(c + kWave, e1);
-                while (ptr[dcur + 1] <= c) ++dcur;  // skip ended and empty documents
-                // lane e belongs to the last document dd with ptr[dd] <= e
-                int64_t mine = dcur, dd = dcur, bnd = ptr[dcur + 1];
-                while (bnd < cend) {
-                    ++dd;
-                    if (e >= bnd) mine = dd;
-                    bnd = ptr[dd + 1];
-                }
-                const int32_t j = rj[u];
-                const bool act0 = e < e1 && rk[u] != 0u && j >= j0 && j < j1;
-                for (int64_t gd = dcur; gd <= dd; ++gd) {
-                    if (act0 && mine == gd) {
-                        const uint32_t slot = atomicAdd(&cur[j - j0], 1u);
-                        const int64_t pos = P0 + slot;
-                        post_doc[pos] = (uint16_t)((gd - d0) * 4);
-                        const float v = rv[u];
-                        if (dtype == SINDI_F32) reinterpret_cast<float *>(post_val)[pos] = v;
-                        else
-                            reinterpret_cast<uint16_t *>(post_val)[pos] =
-                                dtype == SINDI_F16 ? f16_bits(v) : bf16_bits(v);
-                    }
-                    wave_sync();
-                }
-                dcur = dd;
+    for (int u = 0; u < P; ++u) up_j[u] = -1;
+    __syncthreads();
+    while (e < e1) {
+        const int64_t *bnd = s_bnd[buf];
+        // documents d .. d + nb - 1 whole (entries [e, eb)), or part of document d (nb = 0)
+        int nb = 0;
+#pragma unroll
+        for (int k = 1; k <= kFillDocs; ++k)
+            if (nb == k - 1 && d + k <= d1 && bnd[k] - e <= kFillCap) nb = k;
+        const int64_t eb = nb ? bnd[nb] : e + kFillCap;
+        fetch(eb, nj, nk, nv);
+        int32_t jj[P];
+        uint32_t bit[P];
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (up_j[u] >= 0) atomicAdd(&word[up_j[u] - j0], up_d[u]);
+            const int64_t x = e + tid + (int64_t)u * kFillThreads;
+            jj[u] = -1;
+            bit[u] = 0;
+            if (x < eb && rk[u] != 0u && rj[u] >= j0 && rj[u] < j1) {
+                int b = 0;  // the entry's document in the batch
+#pragma unroll
+                for (int k = 1; k < kFillDocs; ++k) b += (k < nb && bnd[k] <= x) ? 1 : 0;
+                jj[u] = rj[u];
+                bit[u] = (uint32_t)b;
+                atomicAdd(&word[rj[u] - j0], 1u << (16 + b));
             }
-            fetch(c + (int64_t)R * kWave, u);
         }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            up_j[u] = -1;
+            if (jj[u] < 0) continue;
+            const uint32_t wd = word[jj[u] - j0];
+            const uint32_t bits = wd >> 16;
+            const uint32_t slot = (wd & 0xFFFFu) + (uint32_t)__popc(bits & ((1u << bit[u]) - 1u));
+            const int64_t pos = P0 + 4ll * (int64_t)(go[u] & kGoffMask) + slot;
+            post_doc[pos] = (uint16_t)((d + bit[u] - d0) * 4);
+            const float v = rv[u];
+            if (dtype == SINDI_F32) reinterpret_cast<float *>(post_val)[pos] = v;
+            else
+                reinterpret_cast<uint16_t *>(post_val)[pos] = dtype == SINDI_F16 ? f16_bits(v) : bf16_bits(v);
+            if ((bits >> (bit[u] + 1)) == 0u) {  // the batch's last document holding the term
+                up_j[u] = jj[u];
+                up_d[u] = (uint32_t)__popc(bits) - (bits << 16);
+            }
+        }
+        const int64_t dn = nb ? d + nb : d;
+        if (tid <= kFillDocs) s_bnd[buf ^ 1][tid] = ptr[min(dn + tid, d1)];
+        offsets(nj, nk);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            rj[u] = nj[u];
+            rk[u] = nk[u];
+            rv[u] = nv[u];
+        }
+        d = dn;
+        e = eb;
+        buf ^= 1;
     }
 }
 
@@ -548,7 +713,7 @@ hipError_t build_fill_lists(const int64_t *ptr, const int32_t *idx, const float 
     const size_t lds = (size_t)pass_terms * 4;
     hipError_t e = set_lds(k_fill_lists, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_lists, dim3((unsigned)n_tiles, (unsigned)passes), dim3(kWave), lds, s,
+    hipLaunchKernelGGL(k_fill_lists, dim3((unsigned)n_tiles, (unsigned)passes), dim3(kFillThreads), lds, s,
                        ptr, idx, val, keep, tile_doc, tile_post, goff, n_cols, dtype, pass_terms,
                        post_doc, post_val);
     return hipGetLastError();

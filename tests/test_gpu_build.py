@@ -162,3 +162,40 @@ def test_device_build_rejections(sindi):
         sindi.Index(bad, window=10, prune="lp", list_len=3, gpu_build=True)
     with pytest.raises(E, match="gpu_build"):
         sindi.Index(sindi.DeviceCsr.from_host(over), alpha=1.0, window=10)
+
+
+def test_device_build_every_row_width_value_range_and_ties(sindi):
+    """Rows of every width the pruning kernel sorts in registers (up to 64, 128, 256 and 512
+    entries) and beyond (the one-workgroup path, and documents longer than the fill's batch of
+    4,096 entries), rows whose values span more than 2^20 (their mass sums run one after
+    another) beside rows of nearby values (summed by a scan that no rounding touches), and
+    equal magnitudes (Def. 6: the lower term id first): the oracle's Alg. 3 and Alg. 1."""
+    rng = np.random.default_rng(17)
+    vocab = 20_000
+    lens = np.concatenate([rng.integers(0, 65, 300), rng.integers(65, 129, 200),
+                           rng.integers(129, 257, 150), rng.integers(257, 513, 120),
+                           rng.integers(513, 4_000, 12), rng.integers(4_097, 8_193, 6), [0, 1, 512, 8_192]])
+    rng.shuffle(lens)
+    rows_i, rows_v = [], []
+    for r, n in enumerate(lens):
+        ids = np.sort(rng.choice(vocab, size=int(n), replace=False)).astype(np.int32)
+        if r % 5 == 0:  # wide range: magnitudes from 1e-12 to 1e12
+            v = 10.0 ** rng.uniform(-12, 12, size=int(n))
+        elif r % 5 == 1:  # few distinct magnitudes: many ties
+            v = rng.choice([0.25, 0.5, 1.0, 3.0], size=int(n))
+        else:
+            v = rng.lognormal(0.0, 0.8, size=int(n))
+        v = (v * rng.choice([-1.0, 1.0], size=int(n))).astype(np.float32)
+        rows_i.append(ids)
+        rows_v.append(v)
+    indptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    c = synth.Csr(indptr, np.concatenate(rows_i), np.concatenate(rows_v), vocab)
+    queries = synth.random_csr(rng, 16, vocab, 30, signed=True, min_nnz=1)
+    for prune, kw in (("mrp", dict(alpha=0.5)), ("mrp", dict(alpha=0.93)), ("vnp", dict(vn=200))):
+        h = sindi.Index(c, window=300, tile=150, prune=prune, value_dtype="f32", **kw)
+        g = sindi.Index(c, window=300, tile=150, prune=prune, value_dtype="f32", gpu_build=True, **kw)
+        _same_index(h, g)
+        _same_search(h, g, queries)
+        keep = _oracle_keep(c, prune, kw)
+        assert g.info()["n_postings"] == int(keep.sum())
+        check_layout_against_oracle(g.export(), oracle.build_index(c, 300, keep), vocab, 300, "f32")
