@@ -32,11 +32,12 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWaveRow = 512;     // longest row pruned by one wave
 constexpr int kRowsPerWg = 4;     // waves (rows) per workgroup of k_prune_rows
+constexpr int kCheckRows = 16;    // rows per wave of k_check_rows
 constexpr int kCountThreads = 1024;  // k_count_lists workgroup
 constexpr int kCountTerms = 32768;   // 16-bit list counters per pass of k_count_lists (64 KB)
 constexpr int kFillThreads = 1024;   // k_fill_lists workgroup
 constexpr int kFillDocs = 16;        // documents placed together by k_fill_lists (one bit each)
-constexpr int kFillPer = 4;          // entries per thread and batch of k_fill_lists
+constexpr int kFillPer = 2;          // entries per thread and batch of k_fill_lists
 constexpr int64_t kFillCap = (int64_t)kFillThreads * kFillPer;  // entries per batch
 
 // Waits for this wave's LDS operations so that every lane sees the others'.
@@ -96,28 +97,60 @@ __device__ int64_t mass_prefix(const double *s, int64_t m, double alpha)
 }
 
 // err bits: 1 row pointers, 2 term id range, 4 ids not ascending, 8 non-finite.
-// One wave per row.
+// One wave per kCheckRows consecutive rows: their row pointers one per lane,
+// then the rows' entries swept as one range (an entry is the last of its row
+// where the next one starts a row).  Entries are read only when every pointer
+// of the wave's rows is in order and within the arrays.
 __global__ __launch_bounds__(256) void k_check_rows(const int64_t *ptr, const int32_t *idx,
                                                     const float *val, int64_t n_rows,
                                                     int64_t n_cols, int64_t nnz, int32_t *err)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    if (row >= n_rows) return;
-    const int64_t a = ptr[row], b = ptr[row + 1];
+    const int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave * kCheckRows;
+    if (r0 >= n_rows) return;
+    const int nr = (int)min((int64_t)kCheckRows, n_rows - r0);
+    const int64_t p = lane <= nr ? ptr[r0 + lane] : 0;
+    const int64_t pn = __shfl_down(p, 1, kWave);
     int bad = 0;
-    if (a < 0 || b < a || b > nnz || (row == 0 && a != 0) || (row == n_rows - 1 && b != nnz))
-        bad |= 1;
-    if (!bad)
-        for (int64_t e = a + lane; e < b; e += kWave) {
-            const int32_t id = idx[e];
-            if (id < 0 || id >= n_cols) bad |= 2;
-            if (e + 1 < b && idx[e + 1] <= id) bad |= 4;
-            if (!isfinite(val[e])) bad |= 8;
+    if (lane < nr && (p < 0 || pn < p || pn > nnz)) bad |= 1;
+    if (lane == 0 && r0 == 0 && p != 0) bad |= 1;
+    if (lane == nr && r0 + nr == n_rows && p != nnz) bad |= 1;
+    if (__ballot(bad != 0)) {
+        if (bad) atomicOr(err, bad);
+        return;
+    }
+    __shared__ int64_t s_b[4][kCheckRows + 1];  // the row starts, per wave of the workgroup
+    int64_t *rb = s_b[threadIdx.x / kWave];
+    if (lane <= nr) rb[lane] = p;
+    wave_sync();
+    const int64_t ea = rb[0], eb = rb[nr];
+    int k = 0;  // the row of the lane's current entry (entries rise through the sweep)
+    for (int64_t e0 = ea + lane; e0 < eb; e0 += 4 * kWave) {
+        int32_t id[4], nx[4];
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + (int64_t)u * kWave;
+            id[u] = 0;
+            nx[u] = INT32_MAX;
+            v[u] = 0.0f;
+            if (e < eb) {
+                id[u] = idx[e];
+                v[u] = val[e];
+                if (e + 1 < eb) nx[u] = idx[e + 1];
+            }
         }
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) bad |= __shfl_xor(bad, m, kWave);
-    if (bad && lane == 0) atomicOr(err, bad);
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + (int64_t)u * kWave;
+            if (e >= eb) continue;
+            if (id[u] < 0 || id[u] >= n_cols) bad |= 2;
+            if (!isfinite(v[u])) bad |= 8;
+            while (rb[k + 1] <= e) ++k;  // rb[nr] = eb > e ends it
+            if (rb[k + 1] != e + 1 && nx[u] <= id[u]) bad |= 4;  // e is not its row's last
+        }
+    }
+    if (bad) atomicOr(err, bad);  // rare: every lane that found a fault
 }
 
 // Def. 6 order as one unsigned 64-bit key: |x| bits (a positive finite float
@@ -406,24 +439,49 @@ __global__ __launch_bounds__(kCountThreads) void k_count_lists(
         __syncthreads();
         uint32_t kept = 0;
         bool bad = false;
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-            if (!keep[e]) continue;
-            const int32_t j = idx[e];
-            if (j < j0 || j >= j1) continue;
-            ++kept;
-            const uint32_t r = (uint32_t)(j - j0);
-            atomicAdd(&c16[r >> 1], (r & 1u) ? 0x10000u : 1u);
-            const float v = val[e];
-            float sv = v;
-            if (dtype == SINDI_F16) {
-                if (fabsf(v) > 65504.0f) bad = true;
-                sv = (float)__builtin_bit_cast(_Float16, f16_bits(v));
-            } else if (dtype == SINDI_BF16) {
-                sv = __uint_as_float((uint32_t)bf16_bits(v) << 16);
-                if (isinf(sv)) bad = true;
+        // four entries per thread at once: their loads, then the maxima read so far (a
+        // stale value only lets an atomic through), then the counts and updates
+        constexpr int U = 4;
+        for (int64_t base = e0 + threadIdx.x; base < e1; base += (int64_t)blockDim.x * U) {
+            int32_t jv[U];
+            float vv[U];
+            uint32_t kv[U], tm[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {  // unconditional: the lines are read either way
+                const int64_t e = base + (int64_t)u * blockDim.x;
+                jv[u] = -1;
+                vv[u] = 0.0f;
+                kv[u] = 0u;
+                if (e < e1) {
+                    kv[u] = keep[e];
+                    jv[u] = idx[e];
+                    vv[u] = val[e];
+                }
             }
-            const uint32_t bits = __float_as_uint(fabsf(sv));
-            if (bits > term_max_bits[j]) atomicMax(&term_max_bits[j], bits);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!kv[u] || jv[u] < j0 || jv[u] >= j1) jv[u] = -1;
+                tm[u] = jv[u] >= 0 ? term_max_bits[jv[u]] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t j = jv[u];
+                if (j < 0) continue;
+                ++kept;
+                const uint32_t r = (uint32_t)(j - j0);
+                atomicAdd(&c16[r >> 1], (r & 1u) ? 0x10000u : 1u);
+                const float v = vv[u];
+                float sv = v;
+                if (dtype == SINDI_F16) {
+                    if (fabsf(v) > 65504.0f) bad = true;
+                    sv = (float)__builtin_bit_cast(_Float16, f16_bits(v));
+                } else if (dtype == SINDI_BF16) {
+                    sv = __uint_as_float((uint32_t)bf16_bits(v) << 16);
+                    if (isinf(sv)) bad = true;
+                }
+                const uint32_t bits = __float_as_uint(fabsf(sv));
+                if (bits > tm[u]) atomicMax(&term_max_bits[j], bits);
+            }
         }
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) kept += __shfl_xor(kept, d, kWave);
@@ -556,6 +614,9 @@ __global__ __launch_bounds__(kFillThreads) void k_fill_lists(
         for (int k = 1; k <= kFillDocs; ++k)
             if (nb == k - 1 && d + k <= d1 && bnd[k] - e <= kFillCap) nb = k;
         const int64_t eb = nb ? bnd[nb] : e + kFillCap;
+        const int64_t dn = nb ? d + nb : d;
+        int64_t pnext = 0;  // the next batch's row pointers, stored after this phase
+        if (tid <= kFillDocs) pnext = ptr[min(dn + tid, d1)];
         fetch(eb, nj, nk, nv);
         int32_t jj[P];
         uint32_t bit[P];
@@ -593,8 +654,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill_lists(
                 up_d[u] = (uint32_t)__popc(bits) - (bits << 16);
             }
         }
-        const int64_t dn = nb ? d + nb : d;
-        if (tid <= kFillDocs) s_bnd[buf ^ 1][tid] = ptr[min(dn + tid, d1)];
+        if (tid <= kFillDocs) s_bnd[buf ^ 1][tid] = pnext;
         offsets(nj, nk);
         __syncthreads();
 #pragma unroll
@@ -646,7 +706,8 @@ hipError_t build_check_rows(const int64_t *ptr, const int32_t *idx, const float 
                             hipStream_t s)
 {
     if (n_rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_check_rows, dim3(blocks_for(n_rows * kWave, 256)), dim3(256), 0, s, ptr,
+    hipLaunchKernelGGL(k_check_rows, dim3(blocks_for((n_rows + kCheckRows - 1) / kCheckRows * kWave, 256)),
+                       dim3(256), 0, s, ptr,
                        idx, val, n_rows, n_cols, nnz, err);
     return hipGetLastError();
 }

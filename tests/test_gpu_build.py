@@ -164,6 +164,48 @@ def test_device_build_rejections(sindi):
         sindi.Index(sindi.DeviceCsr.from_host(over), alpha=1.0, window=10)
 
 
+def test_device_corpus_structure_check(sindi):
+    """The device's check of a corpus in HBM (Def. 1: row pointers, term id range, ascending
+    ids inside every row, finite values) over corpora of many rows, the faults placed in rows
+    far from the first; ids that fall from one row to the next are no fault."""
+    E = sindi.SindiError
+    rng = np.random.default_rng(9)
+    n_rows, n_cols = 45, 64
+    rows = [np.sort(rng.choice(n_cols, size=int(rng.integers(0, 9)), replace=False)) for _ in range(n_rows)]
+    rows[17] = np.array([60, 61, 62], np.int64)  # then row 18 starts low: no fault
+    rows[18] = np.array([0, 1], np.int64)
+    indptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    good = synth.Csr(indptr, np.concatenate(rows).astype(np.int32),
+                     rng.lognormal(0, 0.8, size=int(indptr[-1])).astype(np.float32), n_cols)
+    h = sindi.Index(good, alpha=0.5, window=20)
+    g = sindi.Index(sindi.DeviceCsr.from_host(good), alpha=0.5, window=20, gpu_build=True)
+    _same_index(h, g)
+
+    def faulty(change):
+        c = synth.Csr(good.indptr.copy(), good.indices.copy(), good.values.copy(), n_cols)
+        change(c)
+        return sindi.DeviceCsr.from_host(c)
+
+    cases = {
+        # id out of range on the last entry of a row (so the order inside the row holds)
+        "0x2": lambda c: c.indices.__setitem__(
+            int(c.indptr[next(r for r in range(33, n_rows) if c.indptr[r + 1] > c.indptr[r]) + 1]) - 1,
+            n_cols),
+        "0x8": lambda c: c.values.__setitem__(int(c.indptr[-1]) - 1, np.inf),  # non-finite
+        "0x1": lambda c: c.indptr.__setitem__(30, c.indptr[31] + 1),  # pointers fall
+    }
+    for flag, change in cases.items():
+        with pytest.raises(E, match="flags " + flag):
+            sindi.Index(faulty(change), alpha=0.5, window=20, gpu_build=True)
+    # ids not ascending inside a row past the first wave's 16 rows
+    k = next(r for r in range(20, n_rows) if good.indptr[r + 1] - good.indptr[r] >= 2)
+    c = synth.Csr(good.indptr.copy(), good.indices.copy(), good.values.copy(), n_cols)
+    a = int(c.indptr[k])
+    c.indices[a], c.indices[a + 1] = c.indices[a + 1], c.indices[a]
+    with pytest.raises(E, match="flags 0x4"):
+        sindi.Index(sindi.DeviceCsr.from_host(c), alpha=0.5, window=20, gpu_build=True)
+
+
 def test_device_build_every_row_width_value_range_and_ties(sindi):
     """Rows of every width the pruning kernel sorts in registers (up to 64, 128, 256 and 512
     entries) and beyond (the one-workgroup path, and documents longer than the fill's batch of
