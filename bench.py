@@ -417,6 +417,8 @@ def main():
                 ("mrp", dict(alpha=0.5)), ("vnp", dict(vn=22)), ("lp", dict(list_len=20_000)),
                 ("mrp+lp", dict(alpha=0.5, list_len=20_000))]))
         if not args.no_sweep and main_leg:
+            optional_leg(result, "layout",
+                         lambda: layout_leg(sindi, corpus, dq, alpha, dtype, gamma, k, ids, scores))
             idx.close()  # room for the sweep's indexes
             optional_leg(result, "sweep",
                          lambda: sweep_leg(sindi, corpus, dq, wl, k, tsel, truth_t, rec_note))
@@ -497,6 +499,48 @@ def sweep_leg(sindi, corpus, dq, wl, k, tsel, truth, rec_note, steps=3):
     return {"grid": "alpha {0.2,0.3,0.4,0.5} x gamma {200,500} x beta {0.8,1.0} x {f16,f32}",
             "recall_sample": rec_note, "steps": steps, "config_point": cfg,
             "best_at_recall_0.99": best, "rows": rows}
+
+
+def layout_leg(sindi, corpus, dq, alpha, dtype, gamma, k, ref_ids, ref_scores, steps=3):
+    """Window lambda and score tile T (the GPU's analog of Sec. 3.3.1's window size): tiles of at
+    most T documents split each window equally, and one workgroup holds one tile's scores in
+    LDS.  Each layout is built on the device and searched over the whole query set; Thm. 3.1
+    makes the work, and the fixed-point sums make the results, the same in every layout, which
+    the leg checks against the configuration point's ids and scores bit for bit."""
+    import torch
+    n_q = dq.n_rows
+    ids = torch.empty_like(ref_ids)
+    sc = torch.empty_like(ref_scores)
+    rows = []
+    for window, tile in ((100_000, 5_000), (100_000, 6_250), (100_000, 8_334), (100_000, 10_000),
+                         (100_000, 12_500), (100_000, 14_286), (25_000, 12_500), (30_000, 12_500),
+                         (1_000_000, 12_500), (corpus.n_rows, 12_500)):
+        idx = sindi.Index(corpus, alpha=alpha, window=window, value_dtype=dtype, tile=tile,
+                          gpu_build=True)
+        info = idx.info()
+        idx.search(dq, k, gamma=gamma, out=(ids, sc))
+        torch.cuda.synchronize()
+        sindi.profile_enable(True)
+        sindi.profile_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            idx.search(dq, k, gamma=gamma, out=(ids, sc))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = sindi.profile_read(reset=True)
+        sindi.profile_enable(False)
+        n_launch, acc_ms = prof["accumulate_score"]
+        rows.append({"window": window, "tile_max": info["tile_max"], "n_tiles": info["n_tiles"],
+                     "qps": round(n_q * steps / el, 1),
+                     "score_pass_ms": round(acc_ms / max(n_launch, 1), 3),
+                     "same_results": bool(torch.equal(ids, ref_ids)
+                                          and torch.equal(sc.view(torch.int32),
+                                                          ref_scores.view(torch.int32)))})
+        log(f"layout {rows[-1]}")
+        idx.close()
+        del idx
+    return {"grid": "(window, tile) pairs, tiles splitting each window equally", "steps": steps,
+            "rows": rows}
 
 
 def coarse_error(idx, dqs, qs, pruned, k):

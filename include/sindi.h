@@ -99,7 +99,8 @@ typedef struct {
     double beta;             /* query mass-ratio pruning for the coarse stage, (0, 1]; 0 -> 1 */
     int32_t gamma;           /* reorder pool size, k <= gamma <= 4096; 0 -> max(k, 500)      */
     int32_t batch;           /* queries sharing one pass over a tile's lists: 1, 2, 4 or 8;
-                                0 -> library default                                        */
+                                0 -> library default (1); halved while the batch's score
+                                rows exceed the device's LDS (12,500-document tiles: 2)    */
     int32_t cand_cap;        /* per-query candidate buffer entries; 0 -> library default     */
     int32_t sample_tiles;    /* tiles scored first to set each query's candidate threshold;
                                 0 -> library default, -1 -> no threshold (keep every doc)    */
