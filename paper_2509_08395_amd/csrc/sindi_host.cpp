@@ -192,6 +192,9 @@ sindi_status validate_host_csr(const sindi_csr *m, const char *what, int64_t max
         static const char *msg[] = {"", "row pointers not monotone", "term id out of range",
                                     "term ids not strictly ascending (duplicate or unsorted)",
                                     "non-finite value", "row has too many entries"};
+        if (bad_kind.load() == 5)
+            return fail(SINDI_E_INVALID, "%s: row %lld: more than %lld entries", what,
+                        (long long)bad_row.load(), (long long)max_row);
         return fail(SINDI_E_INVALID, "%s: row %lld: %s", what, (long long)bad_row.load(),
                     msg[bad_kind.load()]);
     }

@@ -600,3 +600,38 @@ def test_persistent_queue_schedule_is_bit_identical(sindi, small, kw):
         a_ids, a_sc = map(_np, fn(queries, k, schedule=1, **extra, **kw))
         b_ids, b_sc = map(_np, fn(queries, k, schedule=2, **extra, **kw))
         assert (a_ids == b_ids).all() and a_sc.tobytes() == b_sc.tobytes()
+
+
+def test_largest_pool_longest_query_and_largest_tile(sindi):
+    """The limits the interface states, at once: gamma = k = 4096 (the largest pool), a query
+    of 4,096 terms (the longest the rerank's query table holds; 64 register segments per
+    scoring wave) beside short ones, and tiles of 16,384 documents (the largest; two
+    workgroups per CU) with a ragged last window and tile: Alg. 4 of the oracle on the same
+    index, and one term more is refused."""
+    vocab = 6_000
+    corpus = synth.generate(40_003, vocab, nnz=("poisson", 30.0), seed=23)
+    short = synth.generate(6, vocab, nnz=("poisson", 20.0), seed=23, stream=1)
+    rng = np.random.default_rng(23)
+    long_ids = np.sort(rng.choice(vocab, size=4_096, replace=False)).astype(np.int32)
+    long_vals = rng.lognormal(0.0, 0.8, size=4_096).astype(np.float32)
+    q = synth.Csr(np.concatenate([short.indptr, [short.indptr[-1] + 4_096]]).astype(np.int64),
+                  np.concatenate([short.indices, long_ids]),
+                  np.concatenate([short.values, long_vals]), vocab)
+    alpha, gamma, k, window = 0.6, 4_096, 4_096, 32_768
+    idx = sindi.Index(corpus, alpha=alpha, window=window, tile=16_384)
+    assert idx.info()["tile_max"] == 16_384  # two tiles per window, then a ragged window of 7,235
+    ids, sc = map(_np, idx.search(q, k, gamma=gamma))
+    keep = oracle.mass_prune(corpus, alpha)
+    ref = oracle.build_index(corpus, window, keep)
+    rid, rsc, pid, psc = oracle.approx_search(ref, corpus, q, 1.0, gamma, k, want_pool=True)
+    check_ranked(ids, sc)
+    check_scores(corpus, q, ids, sc, rtol=1e-5)
+    check_same_topk(ids, rid, rsc, _tol_kth(corpus, q, rid, rsc, 1e-5),
+                    pool_margin=_pool_margin(pid, psc, oracle.apply_mask(corpus, keep), q, 1e-5))
+    too_long = synth.Csr(np.array([0, 4_097], np.int64),
+                         np.sort(rng.choice(vocab, size=4_097, replace=False)).astype(np.int32),
+                         np.ones(4_097, np.float32), vocab)
+    with pytest.raises(sindi.SindiError, match="4096"):
+        idx.search(too_long, 10)
+    with pytest.raises(sindi.SindiError, match="gamma"):
+        idx.search(short, 10, gamma=4_097)
