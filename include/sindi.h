@@ -101,15 +101,17 @@ typedef struct {
     int32_t batch;           /* queries sharing one pass over a tile's lists: 1, 2, 4 or 8;
                                 0 -> library default (1); halved while the batch's score
                                 rows exceed the device's LDS (12,500-document tiles: 2)    */
-    int32_t cand_cap;        /* per-query candidate buffer entries; 0 -> library default     */
+    int32_t cand_cap;        /* per-query candidate buffer entries; 0 -> 32768               */
     int32_t sample_tiles;    /* tiles scored first to set each query's candidate threshold;
-                                0 -> library default, -1 -> no threshold (keep every doc)    */
-    int32_t tile_run;        /* consecutive tiles swept by one workgroup; 0 -> default       */
+                                0 -> 8, -1 -> no threshold (keep every document)             */
+    int32_t tile_run;        /* consecutive tiles swept by one workgroup; 0 -> 16; halved
+                                while a launch would hold fewer than 4096 (query, tile
+                                run) items                                                  */
     int32_t schedule;        /* scoring launches with one query per workgroup: 1 one
                                 workgroup per (query, tile run); 2 one persistent launch of
                                 the workgroups the device holds at once, each taking (query,
                                 tile run) items from a device queue until it is empty;
-                                0 -> library default.  Results are the same bit for bit.    */
+                                0 -> 2.  Results are the same bit for bit.                  */
 } sindi_search_params;
 
 /* Summary of a built index. */
