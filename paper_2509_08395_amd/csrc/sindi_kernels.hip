@@ -3,9 +3,11 @@
 //   k_query_prep   validate query rows; beta-mass subvector (Def. 6, Sec. 4.1)
 //   k_accumulate1  stream each query term's window list I_{j,w} (Alg. 2,
 //                  product + accumulate steps) into an on-chip score tile,
-//                  one query per workgroup; then either sample per-thread
+//                  one query per workgroup, the waves taking batches of
+//                  chunks from a counter; then either sample per-thread
 //                  maxima (threshold pass) or emit every tile score at or
-//                  above the query's threshold
+//                  above the query's threshold (k_accumulate1_queue: the same
+//                  as one persistent launch fed by a device queue)
 //   k_accumulate   the same for batches of 2, 4 or 8 queries sharing lists
 //   k_theta        per-query candidate threshold from the sampled maxima
 //   k_finalize     exact top-gamma of the emitted candidates (Alg. 2 heap
@@ -37,6 +39,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kRerankPerWave = 4;  // pool entries one rerank wave scores
+constexpr int kMaxSeg = kQueryHash / 2 / kWave;  // 64-term segments of the longest query
 
 __device__ __forceinline__ uint32_t ord_f32(float f)
 {
@@ -854,13 +857,16 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 
 // The single-query form of k_accumulate (same grid, same scores, same
 // read-out).  Every wave lays out the tile's chunks itself: the query's terms
-// are taken 64 at a time (a segment, one list per lane), a wave-wide prefix
-// sum over the lists' chunk counts numbers the chunks, and the wave keeps its
-// contiguous share of the tile's chunks.  The chunk layout thus needs no LDS
-// table and no barrier: a tile costs the two barriers around its read-out.
-// The first segment's terms, weights and list bounds (the next tile's
-// prefetched during the current one) stay in registers; further segments
-// are reloaded (cache hits) where used.
+// are taken 64 at a time (a segment, one list per lane), and a wave-wide
+// prefix sum over the lists' chunk counts numbers the segment's chunks.  The
+// waves then take batches of KU consecutive chunks from the segment's counter
+// in LDS (one atomic by the wave's first lane, the next batch taken while the
+// current one's loads are in flight), so they finish the tile together however
+// unevenly the lists' lengths and the adds' bank conflicts fall; the counters
+// are cleared between the tile's two barriers.  The layout needs no LDS table:
+// a tile costs the two barriers around its read-out.  The first segment's
+// terms, weights and list bounds (the next tile's prefetched during the
+// current one) stay in registers; further segments are reloaded (cache hits).
 //
 // One work item: query slot `slot` over tile run `run` (tiles [run R, (run + 1) R)).  The
 // score row must be all zero on entry unless clear_row (the read-out of every tile clears what
@@ -872,7 +878,7 @@ __device__ __forceinline__ void accumulate1_item(
     int64_t cap, int32_t tiles_per_wg, int32_t slot, int64_t run, bool clear_row)
 {
     constexpr int NT = kAccThreads, NW = NT / kWave;
-    constexpr int KU = VT == 0 ? 4 : 8;  // chunks in flight per wave
+    constexpr int KU = VT == 0 ? 3 : 5;  // chunks per batch of a wave
     extern __shared__ __align__(16) unsigned char smem[];
     int32_t *A32 = reinterpret_cast<int32_t *>(smem);  // the query's score row [tile_stride]
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -935,6 +941,10 @@ __device__ __forceinline__ void accumulate1_item(
         }
     };
     load_run(r_base);
+    // The waves take batches of KU chunks of a segment from the segment's counter, so that
+    // they reach the tile's barrier together.
+    __shared__ uint32_t s_next[kMaxSeg];
+    for (int i = tid; i < kMaxSeg; i += NT) s_next[i] = 0;
     __syncthreads();
 
     for (int64_t ti = ti_beg; ti < ti_end; ++ti) {
@@ -973,41 +983,33 @@ __device__ __forceinline__ void accumulate1_item(
                 ng = (hi & kGoffMask) - gs;
             }
         };
-        // chunk numbers: list l of a segment holds its chunks [incl - nch, incl)
-        const uint32_t incl0 = wave_incl_scan((ng0 + kChunk - 1) / kChunk);
-        uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl0, kWave - 1);
-        for (int32_t s = 1; s < nseg; ++s) {
-            uint32_t gs, ng;
-            float w;
-            segment(s, gs, ng, w);
-            total += (uint32_t)__builtin_amdgcn_readlane(
-                (int)wave_incl_scan((ng + kChunk - 1) / kChunk), kWave - 1);
-        }
-        const uint32_t c_beg = uni((uint32_t)(((uint64_t)total * (uint32_t)wave) / NW));
-        const uint32_t c_end = uni((uint32_t)(((uint64_t)total * (uint32_t)(wave + 1)) / NW));
         // the tile's groups, addressed by 32-bit byte offsets (a tile holds at most
         // kTileGroupsMax groups; the arrays end with kTailSlots zero postings)
         const gbytes pd_t =
             uni_ptr(reinterpret_cast<const unsigned char *>(ix.post_doc) + G0 * sizeof(uint2));
         const gbytes pv_t =
             uni_ptr(reinterpret_cast<const unsigned char *>(ix.post_val) + G0 * sizeof(Raw));
-        uint32_t off = 0;  // chunks of the segments before s
-        for (int32_t s = 0; s < nseg && off < c_end; ++s) {
-            uint32_t gs = gs0, ng = ng0, incl = incl0;
+        for (int32_t s = 0; s < nseg; ++s) {
+            uint32_t gs = gs0, ng = ng0;
             float wl = w0;
-            if (s > 0) {
-                segment(s, gs, ng, wl);
-                incl = wave_incl_scan((ng + kChunk - 1) / kChunk);
-            }
+            if (s > 0) segment(s, gs, ng, wl);
+            // chunk numbers: list l of the segment holds its chunks [incl - nch, incl)
+            const uint32_t nch = (ng + kChunk - 1) / kChunk;
+            const uint32_t incl = wave_incl_scan(nch);
             const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
-            const uint32_t la = max(c_beg, off) - off, lb = min(c_end, off + st) - off;
-            off += st;
-            if (la >= lb || off <= c_beg) continue;
+            if (st == 0) continue;
             // list of chunk ci: the lanes whose lists end at or before ci, counted
             const uint32_t cpn = incl;
-            const uint32_t basel = gs - (incl - (ng + kChunk - 1) / kChunk) * (uint32_t)kChunk;
+            const uint32_t basel = gs - (incl - nch) * (uint32_t)kChunk;
             const uint32_t endl = gs + ng;
-            for (uint32_t cs = la; cs < lb; cs += KU) {
+            auto take = [&]() {  // the first chunk of the wave's next batch
+                uint32_t g = 0;
+                if (lane == 0) g = atomicAdd(&s_next[s], (uint32_t)KU);
+                return uni(g);
+            };
+            const uint32_t lb = st;
+            uint32_t cs = take();
+            while (cs < lb) {
                 uint2 ids[KU];
                 Raw raw[KU];
                 uint32_t nl[KU];
@@ -1037,6 +1039,7 @@ __device__ __forceinline__ void accumulate1_item(
                     load_at(pv_t, gi * (uint32_t)sizeof(Raw), raw[i]);
                 }
                 __builtin_amdgcn_s_setprio(0);
+                const uint32_t next = take();  // while this batch's loads are in flight
 #pragma unroll
                 for (int i = 0; i < KU; ++i) {
                     if ((uint32_t)lane >= nl[i]) continue;
@@ -1055,9 +1058,11 @@ __device__ __forceinline__ void accumulate1_item(
                 // prefetch) reuses its registers, so those loads never wait.
 #pragma unroll
                 for (int i = 0; i < KU; ++i) __asm__ volatile("" ::"v"(ids[i].x), "v"(raw[i].x));
+                cs = next;
             }
         }
         __syncthreads();
+        if (tid < nseg) s_next[tid] = 0;  // every wave has taken its last batch of the tile
 
         // ---- read the row: sample maxima or emit every score at or above the
         // query's threshold (as in k_accumulate)
