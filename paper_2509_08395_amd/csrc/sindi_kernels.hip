@@ -1655,7 +1655,7 @@ hipError_t run_accumulate(const DevIndex &ix, const DevQueries &q, const DevCoar
     const int64_t n_iter = SAMPLE ? n_sample : ix.n_tiles;
     // Contiguous tile ranges per workgroup (see the kernel); the range length
     // keeps the grid at least a few times the chip's resident workgroups.
-    int64_t per = tiles_per_wg > 0 ? tiles_per_wg : 16;
+    int64_t per = tiles_per_wg > 0 ? tiles_per_wg : 12;
     while (per > 1 && n_batches * ((n_iter + per - 1) / per) < 4096) per >>= 1;
     int64_t groups = (n_iter + per - 1) / per;
     if (groups > 65535) {
