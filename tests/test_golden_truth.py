@@ -27,7 +27,7 @@ def test_stored_exact_topk_is_the_oracles():
     assert meta["n_docs"] == wl.n_docs and meta["seed"] == wl.seed and meta["k"] == wl.k
     corpus, queries = wl.corpus(), wl.queries()
     assert meta["fingerprint"] == mt.fingerprint(corpus, queries)
-    sel = np.array([0, 3_499, 6_999])
+    sel = np.array([0, 6_999])  # each one scans the 1.1e9 corpus entries on one host thread
     got, sc = oracle.exact_topk(corpus, queries.take_rows(sel), wl.k)
     assert np.array_equal(got, ids[sel].astype(np.int64))
     assert np.array_equal(sc.astype(np.float32), scores[sel])
