@@ -145,7 +145,6 @@ constexpr int32_t kDefaultSampleTiles = 8;
 // with one workgroup per (query, tile run); 79.0 against 80.5 ms on the serving mix)
 constexpr int32_t kDefaultSchedule = 2;
 constexpr int32_t kDefaultGamma = 500;
-constexpr int64_t kLongQueryMean = 48;  // mean query terms above which runs are 8 tiles, else 12
 constexpr size_t kCandBudget = size_t(4) << 30;  // candidate buffer bytes per pass
 
 }  // namespace
@@ -638,13 +637,22 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
 // ------------------------------------------------------------------ search
 // Tiles per work item when the call leaves it open.  The workgroups resident together sweep
 // runs of the same tiles, so the lists of a run's tiles are shared through L2 as long as the
-// tiles the workgroups are spread over fit in it; longer queries read more lists per tile, so
-// they take shorter runs.  Measured at 8.8M documents: queries of ~35 terms fastest at 12
-// tiles per run (16: 2.9% slower, 8: 1.3%), the serving mix of 5 to 200 terms at 8 (12: 13%
-// slower, 16: 29%).
-void set_tile_run(Plan &pl, const sindi_search_params &p, int64_t nq, int64_t nnz)
+// tiles the workgroups are spread over fit in it; the more list postings a query reads per
+// tile, the shorter the run.  That load is taken as the index's kept fraction of the corpus
+// entries times the mean query length.  Measured at 8.8M documents (scoring pass per 7,000
+// queries): alpha 0.5 and ~35 terms (x = 7.7) fastest at 12 tiles per run (16: 2.9% slower,
+// 8: 1.3%); the serving mix of 5 to 200 terms (x = 22) at 8 (12: 13% slower, 16: 29%); alpha
+// 0.3 and 0.2 with ~35 terms (x = 3.5 and 1.7) at 24 (12: 4.6% and 5.6% slower).
+void set_tile_run(Plan &pl, const sindi_index *ix, const sindi_search_params &p, int64_t nq,
+                  int64_t nnz)
 {
-    pl.tile_run = p.tile_run ? p.tile_run : (nq > 0 && nnz > kLongQueryMean * nq ? 8 : 12);
+    if (p.tile_run) {
+        pl.tile_run = p.tile_run;
+        return;
+    }
+    const double kept = ix->nnz > 0 ? (double)ix->n_post / (double)ix->nnz : 1.0;
+    const double x = nq > 0 ? kept * (double)nnz / (double)nq : 0.0;
+    pl.tile_run = x > 12.0 ? 8 : (x > 5.0 ? 12 : 24);
 }
 
 sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
@@ -930,7 +938,7 @@ sindi_status search_impl(sindi_index *ix, const sindi_csr *qc, int32_t k,
     sindi_status st = make_plan(ix, nq, k, p, rerank, fn, pl);
     if (st != SINDI_OK) return st;
     if (nq == 0) return SINDI_OK;
-    set_tile_run(pl, p, nq, qc->nnz);
+    set_tile_run(pl, ix, p, nq, qc->nnz);
     if (qc->on_device && (!qc->indptr || (qc->nnz > 0 && (!qc->indices || !qc->values))))
         return fail(SINDI_E_INVALID, "%s: null query array", fn);
     int64_t longest = 0;

@@ -64,7 +64,7 @@ sindi_status noalloc_impl(const sindi_index *ix, const sindi_csr *qc, int32_t k,
     sindi_status st = make_plan(ix, qc->n_rows, k, p, true, fn, pl);
     if (st != SINDI_OK) return st;
     if (qc->n_rows == 0) return SINDI_OK;
-    set_tile_run(pl, p, qc->n_rows, qc->nnz);
+    set_tile_run(pl, ix, p, qc->n_rows, qc->nnz);
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != ix->device)

@@ -247,7 +247,7 @@ bool sindi_server::launch(Slot &s, std::vector<Request *> &batch)
     s.pl = base;
     s.pl.k = kb;
     s.pl.max_qnnz = longest;  // sizes the kernels' per-query LDS for this batch
-    set_tile_run(s.pl, p.search, nb, nnz);
+    set_tile_run(s.pl, ix, p.search, nb, nnz);
     s.stage = 0;
     s.dq = DevQueries{nb, nnz, s.q_ptr.as<int64_t>(), s.q_idx.as<int32_t>(), s.q_val.as<float>()};
     auto enqueue = [&]() -> sindi_status {

@@ -170,11 +170,13 @@ struct sindi_index {
 namespace sindi {
 
 // Resolve search parameters for nq queries (no device work).
-// The plan's tiles per work item: the caller's, else 12, or 8 when the nq queries' nnz terms
-// average more than 48 (the tiles the resident workgroups share through L2).
-void set_tile_run(Plan &pl, const sindi_search_params &p, int64_t nq, int64_t nnz);
 sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
                        const sindi_search_params &p, bool rerank, const char *fn, Plan &pl);
+// The plan's tiles per work item: the caller's, else 8, 12 or 24 by the list postings the nq
+// queries (nnz terms) read per tile, taken as the index's kept fraction times their mean
+// length (the tiles the resident workgroups share through L2).
+void set_tile_run(Plan &pl, const sindi_index *ix, const sindi_search_params &p, int64_t nq,
+                  int64_t nnz);
 
 // Structural check of a host CSR (Def. 1).  max_row > 0 bounds row length;
 // longest (if not null) receives the longest row.
