@@ -141,8 +141,9 @@ typedef struct sindi_index sindi_index;
  * by ascending term id; the shortest prefix whose |x| sum, accumulated in
  * FP64 in that order, reaches alpha times the row's mass), or pruned by the
  * rule params->prune selects, and the kept entries are laid out as the value-storing inverted lists I_{j,w} of Alg. 1
- * (document ids ascending inside every list), each window further split into
- * score tiles.  The unpruned corpus is kept too, for the exact rerank of
+ * (document ids ascending inside every list; stored in chunks of 256 slots, each
+ * chunk's postings in the LDS-bank order sindi_index_export describes), each
+ * window further split into score tiles.  The unpruned corpus is kept too, for the exact rerank of
  * Alg. 4.  Both live in device memory owned by the returned handle.
  * Values stored as FP16/BF16 are rounded to nearest even; an FP16 overflow
  * (|x| > 65504) returns SINDI_E_RANGE.
@@ -163,10 +164,16 @@ sindi_status sindi_index_get_info(const sindi_index *idx, sindi_index_info *out)
  *   tile_post  int64 [n_tiles + 1]  first posting slot of each tile (multiple of 4)
  *   term_goff  uint32 [n_tiles * (n_cols + 1)]  for tile t and term j, with
  *              g = term_goff[t*(n_cols+1) + j]: the list I_{j,t} starts at slot
- *              tile_post[t] + 4 * (g & 0x3FFFFFFF), holds its postings in
- *              ascending document order, then (g >> 30) pad entries (value
- *              0, document id repeated), and the next term's list starts at the
- *              next 4-slot boundary; entry n_cols holds the tile's slot count / 4
+ *              tile_post[t] + 4 * (g & 0x3FFFFFFF), holds its postings, then
+ *              (g >> 30) pad entries (value 0, the list's largest document id),
+ *              and the next term's list starts at the next 4-slot boundary;
+ *              entry n_cols holds the tile's slot count / 4.  A list's slots
+ *              form chunks of 256 from its start (the last may be shorter), and
+ *              a chunk holds the next documents of the ascending list, n real
+ *              postings ordered for the score row's 32 LDS banks: taken by
+ *              (document mod 32, document), they fill slots 4 (32 h + r) + p
+ *              of the chunk for r = 0..31, h = 0..1, p = 0..3, skipping slots
+ *              at or past n.
  *   post_doc   uint16 [n_slots]  4 * (document id - tile_doc[t]), the byte offset
  *              of the document's 32-bit score in an on-chip score row
  *   post_val   [n_slots] values as stored (4 or 2 bytes each)

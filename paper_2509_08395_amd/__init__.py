@@ -162,8 +162,9 @@ class Index:
         """The device layout copied to host numpy arrays.
 
         raw=True: the stored arrays (lists aligned to 4 slots with pad entries, the
-        encoded group offsets ``term_goff``).  Otherwise the pads are dropped:
-        ``tile_post`` / ``term_off`` [n_tiles, n_cols + 1] are posting offsets of the
+        encoded group offsets ``term_goff``, every chunk of 64 groups in LDS-bank order).
+        Otherwise the pads are dropped and every list is in ascending document order (Alg.
+        1): ``tile_post`` / ``term_off`` [n_tiles, n_cols + 1] are posting offsets of the
         compacted lists and ``post_doc`` / ``post_val`` hold only real postings."""
         inf = self.info()
         nt, nc, nslot = inf["n_tiles"], inf["n_cols"], inf["n_slots"]
@@ -199,8 +200,11 @@ class Index:
         keep[np.repeat(pad_at, pad_n) + rank] = False
         cpost = np.zeros(nt + 1, np.int64)
         np.cumsum(term_off[:, -1], out=cpost[1:])
+        pd, pv = post_doc[keep], post_val[keep]
+        # the stored chunks are in bank order: documents ascending inside each list
+        order = np.lexsort((pd, np.repeat(np.arange(length.size), length.ravel())))
         return {"tile_doc": tile_doc, "tile_post": cpost, "term_off": term_off,
-                "post_doc": post_doc[keep], "post_val": post_val[keep]}
+                "post_doc": pd[order], "post_val": pv[order]}
 
     def term_lengths(self) -> np.ndarray:
         """Postings per term over all tiles (int64 [n_cols]), pads excluded."""

@@ -396,6 +396,8 @@ sindi_status build_device(const sindi_csr *c, const sindi_build_params *p, hipSt
                              p->value_dtype, ix->post_doc.as<uint16_t>(), ix->post_val.p, s));
     HIP_TRY(build_fill_pads(ix->term_goff.as<uint32_t>(), cnt.as<uint32_t>(), ix->tile_post.as<int64_t>(),
                             n_tiles, nc, ix->post_doc.as<uint16_t>(), s));
+    HIP_TRY(build_deal_chunks(ix->term_goff.as<uint32_t>(), ix->tile_post.as<int64_t>(), n_tiles, nc,
+                              (int32_t)vbytes, ix->post_doc.as<uint16_t>(), ix->post_val.p, s));
     HIP_TRY(hipStreamSynchronize(s));
 #undef BUILD_ALLOC
     ix->h_tile_doc = std::move(tile_doc);
@@ -625,6 +627,8 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
     if ((st = up_or_fail(ix->post_doc, post_doc.data(), post_doc.size() * 2, "posting ids")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->post_val, post_val.data(), post_val.size(), "posting values")) != SINDI_OK) return st;
     if ((st = up_or_fail(ix->term_max, term_max.data(), term_max.size() * 4, "term maxima")) != SINDI_OK) return st;
+    HIP_TRY(build_deal_chunks(ix->term_goff.as<uint32_t>(), ix->tile_post.as<int64_t>(), n_tiles, nc,
+                              (int32_t)vbytes, ix->post_doc.as<uint16_t>(), ix->post_val.p, s));
     HIP_TRY(hipStreamSynchronize(s));
     ix->h_tile_doc = std::move(tile_doc);
     *out = guard.release();

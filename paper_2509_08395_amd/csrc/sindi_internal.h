@@ -23,7 +23,8 @@ struct DevIndex {
                                    // pad entries at its end
     const uint16_t *post_doc;      // [n_slots + kTailSlots] 4 * (document id - tile_doc[t]): the
                                    // byte offset of the document's score word in a row; pads
-                                   // repeat the last one
+                                   // repeat the list's largest; each chunk of kChunk groups in
+                                   // LDS-bank order (build_deal_chunks)
     const void *post_val;          // [n_slots + kTailSlots] value (f32 / f16 / bf16 bits); pads
                                    // and the tail hold 0
     const float *term_max;         // [n_cols] largest |stored value| in the term's lists
@@ -172,6 +173,12 @@ hipError_t build_fill_lists(const int64_t *ptr, const int32_t *idx, const float 
                             uint16_t *post_doc, void *post_val, hipStream_t s);
 hipError_t build_fill_pads(const uint32_t *goff, const uint32_t *cnt, const int64_t *tile_post,
                            int64_t n_tiles, int64_t n_cols, uint16_t *post_doc, hipStream_t s);
+// Reorders every list chunk of kChunk groups (ascending by document on entry: run once, after
+// the lists are filled) so that the postings one scoring instruction adds per 32-lane half fall
+// in distinct LDS banks where the chunk allows; pads stay in place.  vbytes: 4 or 2.
+hipError_t build_deal_chunks(const uint32_t *goff, const int64_t *tile_post, int64_t n_tiles,
+                             int64_t n_cols, int32_t vbytes, uint16_t *post_doc, void *post_val,
+                             hipStream_t s);
 
 hipError_t launch_score_forward(const DevIndex &ix, const DevQueries &q, const int64_t *cand,
                                 int32_t n_cand, float *out, hipStream_t s);

@@ -132,3 +132,42 @@ def check_layout_against_oracle(ex, ref, n_cols, window, dtype):
     got = np.ascontiguousarray(ex["post_val"])
     got = got.view(np.uint32) if dtype == "f32" else got.view(np.uint16)
     assert np.array_equal(got[order], stored_value_bits(ref.val, dtype))
+
+
+def check_bank_order(raw, ex):
+    """The stored lists (raw export) against the ascending ones (export()): a list's slots form
+    chunks of 256 from its start; a chunk of n real postings holds the next n documents of the
+    ascending list, which, taken by (document mod 32, document), fill slots 4 (32 h + r) + p
+    for r = 0..31, h = 0..1, p = 0..3, skipping slots at or past n.  Values move with their
+    documents; pads (value 0, the list's largest document) follow the last chunk."""
+    goff = raw["term_goff"]
+    start = 4 * (goff & 0x3FFFFFFF).astype(np.int64)
+    pad = (goff >> 30).astype(np.int64)[:, :-1]
+    length = (np.diff(start, axis=1) - pad).ravel()
+    first = (raw["tile_post"][:-1, None] + start[:, :-1]).ravel()   # raw slot of each list
+    lid = np.repeat(np.arange(length.size), length)
+    i = np.arange(lid.size) - np.repeat(np.cumsum(length) - length, length)  # rank in the list
+    chunk, pos = i // 256, i % 256
+    n = np.minimum(256, length[lid] - 256 * chunk)
+    # sorted postings: the ascending list's items of each chunk, in (doc mod 32, doc) order
+    doc = ex["post_doc"].astype(np.int64)
+    key = lid * (1 << 20) + chunk
+    order = np.lexsort((doc, doc & 31, key))
+    # the fill order's rank of slot pos in a chunk of n postings
+    lane, p = pos // 4, pos % 4
+    r, h = lane & 31, lane >> 5
+    k = np.minimum(n, 4 * r) + np.minimum(np.maximum(n - 128, 0), 4 * r) + 4 * h + p
+    assert ((k >= 0) & (k < n)).all()
+    chunk_first = i - pos                  # rank in the list of the chunk's first item
+    src = order[(np.cumsum(length) - length)[lid] + chunk_first + k]
+    slots = first[lid] + i
+    assert np.array_equal(raw["post_doc"][slots].astype(np.int64), 4 * doc[src])
+    rv, ev = raw["post_val"], ex["post_val"]
+    assert np.array_equal(rv[slots].view(np.uint8), ev[src].view(np.uint8))
+    # pads: value 0, the list's largest document
+    ends = first + length
+    has = np.nonzero(pad.ravel())[0]
+    for j in has[:2000]:
+        a, m = ends[j], pad.ravel()[j]
+        assert (raw["post_doc"][a:a + m] == raw["post_doc"][first[j]:a].max()).all()
+        assert (rv[a:a + m].view(np.uint8) == 0).all()

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_layout_against_oracle
+from parity import check_bank_order, check_layout_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +56,7 @@ def test_device_build_equals_host_build(sindi, dtype, prune, kw):
     h = sindi.Index(corpus, window=7_000, value_dtype=dtype, tile=2_048, prune=prune, **kw)
     g = sindi.Index(corpus, window=7_000, value_dtype=dtype, tile=2_048, prune=prune, gpu_build=True, **kw)
     _same_index(h, g)
+    check_bank_order(g.export(raw=True), g.export())
     _same_search(h, g, queries)
     # Alg. 3 then Alg. 1 as the oracle computes them
     keep = _oracle_keep(corpus, prune, kw)
