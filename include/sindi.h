@@ -173,7 +173,7 @@ sindi_status sindi_index_get_info(const sindi_index *idx, sindi_index_info *out)
  *              postings ordered for the score row's 32 LDS banks: taken by
  *              (document mod 32, document), they fill slots 4 (32 h + r) + p
  *              of the chunk for r = 0..31, h = 0..1, p = 0..3, skipping slots
- *              at or past n.
+ *              at or past n; a chunk of n <= 4 stays ascending.
  *   post_doc   uint16 [n_slots]  4 * (document id - tile_doc[t]), the byte offset
  *              of the document's 32-bit score in an on-chip score row
  *   post_val   [n_slots] values as stored (4 or 2 bytes each)

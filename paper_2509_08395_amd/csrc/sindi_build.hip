@@ -702,8 +702,10 @@ __global__ void k_fill_pads(const uint32_t *goff, const uint32_t *cnt, const int
 // Each chunk of n real postings, ascending by document on entry, is reordered here: its
 // postings taken by (bank, document) fill, in that order, positions 4 (32 h + r) + p for
 // r = 0..31, h = 0..1, p = 0..3 (those below n), so postings of one bank go to successive bins
-// and a bin holds ceil(count / bins) of them at most.  Pads stay at the list's end.  One wave
-// per list; the waves of the grid's column y take the tile's lists y, y + stride, ...
+// and a bin holds ceil(count / bins) of them at most.  A chunk of one group (one lane) keeps its
+// order, and pads stay at the list's end.  Every wave
+// takes 64 consecutive lists of tile blockIdx.x (their offsets loaded together, a list per
+// lane) and reorders the non-empty ones one after another.
 __global__ __launch_bounds__(kDealThreads) void k_deal_chunks(const uint32_t *goff,
                                                               const int64_t *tile_post,
                                                               int64_t n_cols, int32_t vbytes,
@@ -713,87 +715,100 @@ __global__ __launch_bounds__(kDealThreads) void k_deal_chunks(const uint32_t *go
     __shared__ uint32_t s_doc[NW][4 * kChunk], s_val[NW][4 * kChunk];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t t = blockIdx.x;
-    const int64_t stride = (int64_t)gridDim.y * NW;
-    const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
     const int r = lane & 31, h = lane >> 5;
-    for (int64_t j = (int64_t)blockIdx.y * NW + w; j < n_cols; j += stride) {
-        const size_t o = (size_t)t * (size_t)(n_cols + 1) + (size_t)j;
-        const uint32_t g = goff[o];
-        const uint32_t gs = g & kGoffMask, pad = g >> 30;
-        const uint32_t ng = (goff[o + 1] & kGoffMask) - gs;
-        const int64_t base = tile_post[t] + 4 * (int64_t)gs;  // the list's first slot
-        for (uint32_t c0 = 0; c0 < ng; c0 += kChunk) {
-            const uint32_t cg = min(ng - c0, (uint32_t)kChunk);
-            const uint32_t n = 4 * cg - (c0 + cg == ng ? pad : 0u);
-            const int64_t slot = base + 4 * (int64_t)(c0 + (uint32_t)lane);
-            uint2 dw = make_uint2(0u, 0u);
-            uint4 vw = make_uint4(0u, 0u, 0u, 0u);
-            if ((uint32_t)lane < cg) {
-                dw = *reinterpret_cast<const uint2 *>(post_doc + slot);
-                if (vbytes == 4) {
-                    vw = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint32_t *>(post_val) + slot);
-                } else {
-                    const uint2 hv = *reinterpret_cast<const uint2 *>(reinterpret_cast<const uint16_t *>(post_val) + slot);
-                    vw = make_uint4(hv.x & 0xFFFFu, hv.x >> 16, hv.y & 0xFFFFu, hv.y >> 16);
+    const int64_t tile_first = tile_post[t];
+    const int64_t stride = (int64_t)gridDim.y * NW * kWave;
+    for (int64_t j0 = ((int64_t)blockIdx.y * NW + w) * kWave; j0 < n_cols; j0 += stride) {
+        uint32_t gs_l = 0, pad_l = 0, ng_l = 0;
+        if (j0 + lane < n_cols) {
+            const size_t o = (size_t)t * (size_t)(n_cols + 1) + (size_t)(j0 + lane);
+            const uint32_t g = goff[o];
+            gs_l = g & kGoffMask;
+            pad_l = g >> 30;
+            ng_l = (goff[o + 1] & kGoffMask) - gs_l;
+        }
+        for (uint64_t todo = __ballot(ng_l > 1); todo; todo &= todo - 1) {
+            const int li = __builtin_ctzll(todo);
+            const uint32_t gs = (uint32_t)__builtin_amdgcn_readlane((int)gs_l, li);
+            const uint32_t pad = (uint32_t)__builtin_amdgcn_readlane((int)pad_l, li);
+            const uint32_t ng = (uint32_t)__builtin_amdgcn_readlane((int)ng_l, li);
+            const int64_t base = tile_first + 4 * (int64_t)gs;  // the list's first slot
+            for (uint32_t c0 = 0; c0 < ng; c0 += kChunk) {
+                const uint32_t cg = min(ng - c0, (uint32_t)kChunk);
+                if (cg == 1) break;  // the last chunk, one lane: nothing to spread
+                const uint32_t n = 4 * cg - (c0 + cg == ng ? pad : 0u);
+                const int64_t slot = base + 4 * (int64_t)(c0 + (uint32_t)lane);
+                uint2 dw = make_uint2(0u, 0u);
+                uint4 vw = make_uint4(0u, 0u, 0u, 0u);
+                if ((uint32_t)lane < cg) {
+                    dw = *reinterpret_cast<const uint2 *>(post_doc + slot);
+                    if (vbytes == 4) {
+                        vw = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint32_t *>(post_val) + slot);
+                    } else {
+                        const uint2 hv = *reinterpret_cast<const uint2 *>(reinterpret_cast<const uint16_t *>(post_val) + slot);
+                        vw = make_uint4(hv.x & 0xFFFFu, hv.x >> 16, hv.y & 0xFFFFu, hv.y >> 16);
+                    }
                 }
-            }
-            uint32_t doc[4] = {dw.x & 0xFFFFu, dw.x >> 16, dw.y & 0xFFFFu, dw.y >> 16};
-            uint32_t val[4] = {vw.x, vw.y, vw.z, vw.w};
-            bool ok[4];
-            uint32_t bank[4], present = 0;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                ok[p] = (uint32_t)(4 * lane + p) < n;
-                bank[p] = (doc[p] >> 2) & (kLdsBanks - 1);
-                if (ok[p]) present |= 1u << bank[p];
-            }
-            for (int m = 1; m < kWave; m <<= 1) present |= (uint32_t)__shfl_xor((int)present, m);
-            present = (uint32_t)__builtin_amdgcn_readfirstlane((int)present);
-            // rank of each posting under (bank, position); positions ascend with documents
-            uint32_t rank[4] = {0u, 0u, 0u, 0u}, lower = 0;
-            while (present) {
-                const uint32_t v = (uint32_t)__builtin_ctz(present);
-                present &= present - 1;
-                uint64_t m[4];
-                uint32_t acc = lower;
+                uint32_t doc[4] = {dw.x & 0xFFFFu, dw.x >> 16, dw.y & 0xFFFFu, dw.y >> 16};
+                uint32_t val[4] = {vw.x, vw.y, vw.z, vw.w};
+                bool ok[4];
+                uint32_t bank[4], present = 0;
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    m[p] = __ballot(ok[p] && bank[p] == v);
-                    acc += (uint32_t)__popcll(m[p] & below);
+                    ok[p] = (uint32_t)(4 * lane + p) < n;
+                    bank[p] = (doc[p] >> 2) & (kLdsBanks - 1);
+                    if (ok[p]) present |= 1u << bank[p];
+                }
+                for (int m = 1; m < kWave; m <<= 1) present |= (uint32_t)__shfl_xor((int)present, m);
+                present = (uint32_t)__builtin_amdgcn_readfirstlane((int)present);
+                // rank of each posting under (bank, position); positions ascend with documents
+                uint32_t rank[4] = {0u, 0u, 0u, 0u}, lower = 0;
+                while (present) {
+                    const uint32_t v = (uint32_t)__builtin_ctz(present);
+                    present &= present - 1;
+                    bool sel[4];
+                    uint32_t acc = lower;  // + this bank's postings of the lanes below
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        sel[p] = ok[p] && bank[p] == v;
+                        const uint64_t m = __ballot(sel[p]);
+                        acc = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, acc));
+                        lower += (uint32_t)__popcll(m);
+                    }
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        if (sel[p]) rank[p] = acc;
+                        acc += sel[p] ? 1u : 0u;
+                    }
                 }
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    if (ok[p] && bank[p] == v) rank[p] = acc;
-                    acc += (uint32_t)(m[p] >> lane) & 1u;
-                    lower += (uint32_t)__popcll(m[p]);
-                }
-            }
+                for (int p = 0; p < 4; ++p)
+                    if (ok[p]) {
+                        s_doc[w][rank[p]] = doc[p];
+                        s_val[w][rank[p]] = val[p];
+                    }
+                wave_sync();
+                // position 4 lane + p takes the posting of rank k: its place in the fill order
+                const uint32_t r4 = 4u * (uint32_t)r;
+                const uint32_t k0 = min(n, r4) + min(n > 128u ? n - 128u : 0u, r4) + 4u * (uint32_t)h;
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-                if (ok[p]) {
-                    s_doc[w][rank[p]] = doc[p];
-                    s_val[w][rank[p]] = val[p];
+                for (int p = 0; p < 4; ++p)
+                    if (ok[p]) {
+                        doc[p] = s_doc[w][k0 + (uint32_t)p];
+                        val[p] = s_val[w][k0 + (uint32_t)p];
+                    }
+                wave_sync();
+                if ((uint32_t)lane < cg) {
+                    *reinterpret_cast<uint2 *>(post_doc + slot) =
+                        make_uint2(doc[0] | (doc[1] << 16), doc[2] | (doc[3] << 16));
+                    if (vbytes == 4)
+                        *reinterpret_cast<uint4 *>(reinterpret_cast<uint32_t *>(post_val) + slot) =
+                            make_uint4(val[0], val[1], val[2], val[3]);
+                    else
+                        *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(post_val) + slot) =
+                            make_uint2(val[0] | (val[1] << 16), val[2] | (val[3] << 16));
                 }
-            wave_sync();
-            // position 4 lane + p takes the posting of rank k: its place in the fill order
-            const uint32_t r4 = 4u * (uint32_t)r;
-            const uint32_t k0 = min(n, r4) + min(n > 128u ? n - 128u : 0u, r4) + 4u * (uint32_t)h;
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-                if (ok[p]) {
-                    doc[p] = s_doc[w][k0 + (uint32_t)p];
-                    val[p] = s_val[w][k0 + (uint32_t)p];
-                }
-            wave_sync();
-            if ((uint32_t)lane < cg) {
-                *reinterpret_cast<uint2 *>(post_doc + slot) =
-                    make_uint2(doc[0] | (doc[1] << 16), doc[2] | (doc[3] << 16));
-                if (vbytes == 4)
-                    *reinterpret_cast<uint4 *>(reinterpret_cast<uint32_t *>(post_val) + slot) =
-                        make_uint4(val[0], val[1], val[2], val[3]);
-                else
-                    *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(post_val) + slot) =
-                        make_uint2(val[0] | (val[1] << 16), val[2] | (val[3] << 16));
             }
         }
     }
@@ -910,8 +925,8 @@ hipError_t build_deal_chunks(const uint32_t *goff, const int64_t *tile_post, int
 {
     if (n_tiles == 0 || n_cols == 0) return hipSuccess;
     if (n_tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-    // about 64 lists per wave
-    const int64_t cols = std::min<int64_t>(64, std::max<int64_t>(1, n_cols / (64 * (kDealThreads / kWave))));
+    // 64 lists per wave
+    const int64_t cols = std::min<int64_t>(65535, (n_cols + (int64_t)kDealThreads - 1) / kDealThreads);
     hipLaunchKernelGGL(k_deal_chunks, dim3((unsigned)n_tiles, (unsigned)cols), dim3(kDealThreads), 0,
                        s, goff, tile_post, n_cols, vbytes, post_doc, post_val);
     return hipGetLastError();

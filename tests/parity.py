@@ -138,8 +138,9 @@ def check_bank_order(raw, ex):
     """The stored lists (raw export) against the ascending ones (export()): a list's slots form
     chunks of 256 from its start; a chunk of n real postings holds the next n documents of the
     ascending list, which, taken by (document mod 32, document), fill slots 4 (32 h + r) + p
-    for r = 0..31, h = 0..1, p = 0..3, skipping slots at or past n.  Values move with their
-    documents; pads (value 0, the list's largest document) follow the last chunk."""
+    for r = 0..31, h = 0..1, p = 0..3, skipping slots at or past n; a chunk of n <= 4 stays
+    ascending.  Values move with their documents; pads (value 0, the list's largest document)
+    follow the last chunk."""
     goff = raw["term_goff"]
     start = 4 * (goff & 0x3FFFFFFF).astype(np.int64)
     pad = (goff >> 30).astype(np.int64)[:, :-1]
@@ -152,7 +153,7 @@ def check_bank_order(raw, ex):
     # sorted postings: the ascending list's items of each chunk, in (doc mod 32, doc) order
     doc = ex["post_doc"].astype(np.int64)
     key = lid * (1 << 20) + chunk
-    order = np.lexsort((doc, doc & 31, key))
+    order = np.lexsort((doc, np.where(n > 4, doc & 31, 0), key))
     # the fill order's rank of slot pos in a chunk of n postings
     lane, p = pos // 4, pos % 4
     r, h = lane & 31, lane >> 5
