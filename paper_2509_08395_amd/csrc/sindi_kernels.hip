@@ -1009,11 +1009,16 @@ __device__ __forceinline__ void accumulate1_item(
             };
             const uint32_t lb = st;
             uint32_t cs = take();
+            // The list of the wave's last chunk: its chunks end at c_end, its chunk 0 would
+            // start at group l_base, it ends at group l_end, its weight is l_w.  A wave's chunk
+            // numbers only grow inside a segment, so a chunk below c_end is in that list.
+            uint32_t c_end = 0, l_base = 0, l_end = 0;
+            float l_w = 0.0f;
             while (cs < lb) {
                 uint2 ids[KU];
                 Raw raw[KU];
                 uint32_t nl[KU];
-                int32_t kl[KU];
+                float wk[KU];
                 // Loads are unconditional, so they leave back to back: lane l reads
                 // group g0 + l even past its chunk's end (at most 63 groups past the
                 // tile's last group: inside the arrays); those lanes add nothing.
@@ -1024,15 +1029,19 @@ __device__ __forceinline__ void accumulate1_item(
                 for (int i = 0; i < KU; ++i) {
                     const uint32_t ci = cs + (uint32_t)i;
                     uint32_t g0 = 0, nn = 0;
-                    int32_t k = 0;
                     if (ci < lb) {  // wave-uniform
-                        k = (int32_t)__popcll(__ballot(cpn <= ci));
-                        g0 = (uint32_t)__builtin_amdgcn_readlane((int)basel, k) + ci * (uint32_t)kChunk;
-                        nn = min((uint32_t)kChunk,
-                                 (uint32_t)__builtin_amdgcn_readlane((int)endl, k) - g0);
+                        if (ci >= c_end) {  // the next list holding chunks
+                            const int k = (int)__popcll(__ballot(cpn <= ci));
+                            c_end = (uint32_t)__builtin_amdgcn_readlane((int)cpn, k);
+                            l_base = (uint32_t)__builtin_amdgcn_readlane((int)basel, k);
+                            l_end = (uint32_t)__builtin_amdgcn_readlane((int)endl, k);
+                            l_w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl), k));
+                        }
+                        g0 = l_base + ci * (uint32_t)kChunk;
+                        nn = min((uint32_t)kChunk, l_end - g0);
                         g0 = min(g0, n_groups);
                     }
-                    kl[i] = k;
+                    wk[i] = l_w;
                     nl[i] = nn;
                     const uint32_t gi = g0 + (uint32_t)lane;
                     load_at(pd_t, gi * (uint32_t)sizeof(uint2), ids[i]);
@@ -1043,7 +1052,7 @@ __device__ __forceinline__ void accumulate1_item(
 #pragma unroll
                 for (int i = 0; i < KU; ++i) {
                     if ((uint32_t)lane >= nl[i]) continue;
-                    const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl), kl[i]));
+                    const float w = wk[i];
                     // byte offsets of the documents' 32-bit score words
                     const uint32_t d4[4] = {ids[i].x & 0xFFFFu, ids[i].x >> 16, ids[i].y & 0xFFFFu,
                                             ids[i].y >> 16};
@@ -1079,27 +1088,34 @@ __device__ __forceinline__ void accumulate1_item(
         } else {
             auto read_out = [&](auto imp_c) {
                 constexpr bool IMP = decltype(imp_c)::value;
-                for (int base = wave * 256; base < len; base += NW * 256) {
+                const int4 zero = fresh_zero4();  // one per read-out: the loop keeps it live
+                // The wave's 256 scores from base; TAIL: some of them may lie past the tile.
+                auto step = [&](int base, auto tail_c) {
+                    constexpr bool TAIL = decltype(tail_c)::value;
                     const int m0 = base + lane * 4;
                     int4 r = make_int4(0, 0, 0, 0);
-                    if (m0 < len) {
+                    if (!TAIL || m0 < len) {
                         r = *reinterpret_cast<const int4 *>(A32 + m0);
-                        *reinterpret_cast<int4 *>(A32 + m0) = fresh_zero4();
+                        *reinterpret_cast<int4 *>(A32 + m0) = zero;
                     }
                     const bool look = IMP ? ((r.x | r.y | r.z | r.w) != 0)
                                           : max(max(r.x, r.y), max(r.z, r.w)) >= th;
-                    if (__ballot(look) == 0) continue;  // the common case
+                    if (__ballot(look) == 0) return;  // the common case
                     // threshold <= 0: every nonzero sum, negative ones included (the
                     // finalize kernel takes each document left out as a zero)
                     bool ok[4];
-                    ok[0] = (IMP ? r.x != 0 : r.x >= th) && m0 < len;
-                    ok[1] = (IMP ? r.y != 0 : r.y >= th) && m0 + 1 < len;
-                    ok[2] = (IMP ? r.z != 0 : r.z >= th) && m0 + 2 < len;
-                    ok[3] = (IMP ? r.w != 0 : r.w >= th) && m0 + 3 < len;
+                    ok[0] = (IMP ? r.x != 0 : r.x >= th) && (!TAIL || m0 < len);
+                    ok[1] = (IMP ? r.y != 0 : r.y >= th) && (!TAIL || m0 + 1 < len);
+                    ok[2] = (IMP ? r.z != 0 : r.z >= th) && (!TAIL || m0 + 2 < len);
+                    ok[3] = (IMP ? r.w != 0 : r.w >= th) && (!TAIL || m0 + 3 < len);
                     const float sv[4] = {(float)r.x * qinv, (float)r.y * qinv, (float)r.z * qinv,
                                          (float)r.w * qinv};
                     emit_candidates<4>(sv, ok, d0 + m0, count + slot, cand + (size_t)slot * cap, cap);
-                }
+                };
+                // whole steps without bounds checks, then at most one step across the tile's end
+                int base = wave * 256;
+                for (; base + 256 <= len; base += NW * 256) step(base, std::false_type{});
+                if (base < len) step(base, std::true_type{});
             };
             if (imp)
                 read_out(std::true_type{});
