@@ -104,9 +104,9 @@ typedef struct {
     int32_t cand_cap;        /* per-query candidate buffer entries; 0 -> 32768               */
     int32_t sample_tiles;    /* tiles scored first to set each query's candidate threshold;
                                 0 -> 8, -1 -> no threshold (keep every document)             */
-    int32_t tile_run;        /* consecutive tiles swept by one workgroup; 0 -> 8, 12 or 24 by
+    int32_t tile_run;        /* consecutive tiles swept by one workgroup; 0 -> 8, 12 or 32 by
                                 the index's kept fraction of corpus entries times the call's
-                                mean query terms (above 12: 8; above 5: 12; else 24); halved
+                                mean query terms (above 12: 8; above 5: 12; else 32); halved
                                 while a launch would hold fewer than 4096 (query, tile run)
                                 items                                                       */
     int32_t schedule;        /* scoring launches with one query per workgroup: 1 one

@@ -646,7 +646,8 @@ sindi_status build_impl(const sindi_csr *c, const sindi_build_params *p, hipStre
 // entries times the mean query length.  Measured at 8.8M documents (scoring pass per 7,000
 // queries): alpha 0.5 and ~35 terms (x = 7.7) fastest at 12 tiles per run (16: 2.9% slower,
 // 8: 1.3%); the serving mix of 5 to 200 terms (x = 22) at 8 (12: 13% slower, 16: 29%); alpha
-// 0.3 and 0.2 with ~35 terms (x = 3.5 and 1.7) at 24 (12: 4.6% and 5.6% slower).
+// 0.3 and 0.2 with ~35 terms (x = 3.5 and 1.7) at 32 (24: 0.8% and 1.2% slower, 12: 5.6% and
+// 6.9%).
 void set_tile_run(Plan &pl, const sindi_index *ix, const sindi_search_params &p, int64_t nq,
                   int64_t nnz)
 {
@@ -656,7 +657,7 @@ void set_tile_run(Plan &pl, const sindi_index *ix, const sindi_search_params &p,
     }
     const double kept = ix->nnz > 0 ? (double)ix->n_post / (double)ix->nnz : 1.0;
     const double x = nq > 0 ? kept * (double)nnz / (double)nq : 0.0;
-    pl.tile_run = x > 12.0 ? 8 : (x > 5.0 ? 12 : 24);
+    pl.tile_run = x > 12.0 ? 8 : (x > 5.0 ? 12 : 32);
 }
 
 sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,

@@ -172,7 +172,7 @@ namespace sindi {
 // Resolve search parameters for nq queries (no device work).
 sindi_status make_plan(const sindi_index *ix, int64_t nq, int32_t k,
                        const sindi_search_params &p, bool rerank, const char *fn, Plan &pl);
-// The plan's tiles per work item: the caller's, else 8, 12 or 24 by the list postings the nq
+// The plan's tiles per work item: the caller's, else 8, 12 or 32 by the list postings the nq
 // queries (nnz terms) read per tile, taken as the index's kept fraction times their mean
 // length (the tiles the resident workgroups share through L2).
 void set_tile_run(Plan &pl, const sindi_index *ix, const sindi_search_params &p, int64_t nq,
