@@ -18,9 +18,9 @@
 //                    documents in ascending order
 //   k_fill_pads      the pad entries after every list
 //   k_deal_chunks    reorders every chunk of a list (kChunk groups, one per lane
-//                    of a scoring wave) so that the adds of one scoring
-//                    instruction fall in distinct LDS banks where the chunk
-//                    allows (the sums do not depend on the order)
+//                    of a scoring wave) of two or more groups so that the adds
+//                    of one scoring instruction fall in distinct LDS banks
+//                    where the chunk allows (the sums do not depend on the order)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -703,9 +703,9 @@ __global__ void k_fill_pads(const uint32_t *goff, const uint32_t *cnt, const int
 // postings taken by (bank, document) fill, in that order, positions 4 (32 h + r) + p for
 // r = 0..31, h = 0..1, p = 0..3 (those below n), so postings of one bank go to successive bins
 // and a bin holds ceil(count / bins) of them at most.  A chunk of one group (one lane) keeps its
-// order, and pads stay at the list's end.  Every wave
-// takes 64 consecutive lists of tile blockIdx.x (their offsets loaded together, a list per
-// lane) and reorders the non-empty ones one after another.
+// order, and pads stay at the list's end.  A wave takes 64 consecutive lists of tile blockIdx.x
+// at a time (their offsets loaded together, a list per lane; the grid's columns stride over the
+// vocabulary) and reorders those of two or more groups one after another.
 __global__ __launch_bounds__(kDealThreads) void k_deal_chunks(const uint32_t *goff,
                                                               const int64_t *tile_post,
                                                               int64_t n_cols, int32_t vbytes,
