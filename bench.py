@@ -47,6 +47,27 @@ def per_query_postings(qc, term_len):
     return int(term_len[qc.indices].sum())
 
 
+def coarse_queries(qc, beta):
+    """The query terms a scoring pass reads: each row's beta-mass prefix (Sec. 4.1; entries
+    by |q| descending, ties by term id, FP64 sums in that order, the shortest prefix reaching
+    beta times the row's mass), as a CSR of term ids only.  beta = 1 keeps every term."""
+    from types import SimpleNamespace
+    if beta >= 1.0:
+        return qc
+    ptr, idx = [0], []
+    for r in range(qc.n_rows):
+        a, b = int(qc.indptr[r]), int(qc.indptr[r + 1])
+        t, v = qc.indices[a:b], np.abs(qc.values[a:b].astype(np.float64))
+        t, v = t[v > 0], v[v > 0]
+        order = np.lexsort((t, -v))
+        cs = np.cumsum(v[order])
+        n = int(np.searchsorted(cs, beta * cs[-1], side="left")) + 1 if len(cs) else 0
+        idx.append(np.sort(t[order[:n]]))
+        ptr.append(ptr[-1] + n)
+    return SimpleNamespace(n_rows=qc.n_rows, indptr=np.asarray(ptr, np.int64),
+                           indices=np.concatenate(idx) if idx else np.zeros(0, np.int32))
+
+
 def kernel_code_sha256(path):
     """sha256 of a source file without its comments, whitespace runs collapsed: edits to
     comments and layout leave a counter summary of the compiled code valid."""
@@ -139,6 +160,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--gamma", type=int, default=0)
+    ap.add_argument("--beta", type=float, default=None, help="query pruning (Sec. 4.1)")
     ap.add_argument("--recall-queries", type=int, default=0,
                     help="queries the live exact oracle scores (0: 16 to re-check the stored "
                          "exact top-k of every query, or 1,000 without it)")
@@ -207,6 +229,7 @@ def main():
     dtype = args.value_dtype or wl.value_dtype
     alpha = wl.alpha if args.alpha is None else args.alpha
     gamma = args.gamma or wl.gamma
+    beta = wl.beta if args.beta is None else args.beta
     k = wl.k
 
     t = time.time()
@@ -228,7 +251,7 @@ def main():
     dq = sindi.DeviceCsr.from_host(queries)
     ids = torch.empty((n_q, k), dtype=torch.int64, device="cuda")
     scores = torch.empty((n_q, k), dtype=torch.float32, device="cuda")
-    kw = dict(gamma=gamma, batch=args.batch, out=(ids, scores))
+    kw = dict(gamma=gamma, beta=beta, batch=args.batch, out=(ids, scores))
 
     for _ in range(args.warmup):
         idx.search(dq, k, **kw)
@@ -255,9 +278,10 @@ def main():
     vbytes = {"f32": 4, "f16": 2, "bf16": 2}[dtype]
     bpp = 2 + vbytes
     batch = args.batch or 1
-    union_post = batch_union_postings(queries, term_len, batch)
-    query_post = per_query_postings(queries, term_len)
-    offs_bytes = int(queries.nnz) * int(info["n_tiles"]) * 8
+    cq = coarse_queries(queries, beta)
+    union_post = batch_union_postings(cq, term_len, batch)
+    query_post = per_query_postings(cq, term_len)
+    offs_bytes = int(cq.indptr[-1]) * int(info["n_tiles"]) * 8
     algo_bytes = union_post * bpp + offs_bytes
     # one step may split the queries over several scoring launches (candidate memory)
     n_launch, acc_ms = prof["accumulate_score"]
@@ -268,7 +292,7 @@ def main():
     post_per_launch = query_post // launches_per_step
     config = {"workload": wl.name, "n_docs": corpus.n_rows, "vocab": wl.vocab,
               "n_queries": n_q, "value_storage": dtype, "alpha": alpha,
-              "window": wl.window, "gamma": gamma, "k": k, "beta": wl.beta,
+              "window": wl.window, "gamma": gamma, "k": k, "beta": beta,
               "batch": batch, "tile": info["tile_max"], "n_tiles": info["n_tiles"],
               "n_postings": info["n_postings"]}
     traffic = measured_traffic(config)
@@ -361,7 +385,7 @@ def main():
         pruned = oracle.apply_mask(corpus, keep) if not args.no_precision and main_leg else None
         del keep
         t = time.time()
-        o_ids, _ = oracle.approx_search(oidx, corpus, qo, wl.beta, gamma, k, threads=threads)
+        o_ids, _ = oracle.approx_search(oidx, corpus, qo, beta, gamma, k, threads=threads)
         oracle_s = time.time() - t
         agree = oracle.recall_at_k(gids[osel], o_ids)
         log(f"oracle Alg. 4 on {len(osel)} queries: {oracle_s:.1f}s (index {oracle_build_s:.1f}s), "
@@ -369,7 +393,7 @@ def main():
         # single-thread figures, beside the paper's single-thread numbers
         n1 = min(100, n_q)
         t = time.time()
-        oracle.approx_search(oidx, corpus, queries.take_rows(np.arange(n1)), wl.beta, gamma, k,
+        oracle.approx_search(oidx, corpus, queries.take_rows(np.arange(n1)), beta, gamma, k,
                              threads=1)
         st_alg4 = n1 / (time.time() - t)
         ne = min(8, n_q)
@@ -405,7 +429,7 @@ def main():
                             **coarse_error(idx, dqs, qs, pruned, k)}}
             try:
                 prec.update(precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, tsel, truth_t,
-                                          n_q, dqs, qs, pruned))
+                                          n_q, dqs, qs, pruned, beta=beta))
             except Exception as e:  # noqa: BLE001 -- reported in the JSON line
                 log(f"precision leg failed: {type(e).__name__}: {e}")
                 prec["error"] = f"{type(e).__name__}: {e}"
@@ -418,7 +442,8 @@ def main():
                 ("mrp+lp", dict(alpha=0.5, list_len=20_000))]))
         if not args.no_sweep and main_leg:
             optional_leg(result, "layout",
-                         lambda: layout_leg(sindi, corpus, dq, alpha, dtype, gamma, k, ids, scores))
+                         lambda: layout_leg(sindi, corpus, dq, alpha, dtype, gamma, k, ids, scores,
+                                            beta=beta))
             idx.close()  # room for the sweep's indexes
             optional_leg(result, "sweep",
                          lambda: sweep_leg(sindi, corpus, dq, wl, k, tsel, truth_t, rec_note))
@@ -501,7 +526,8 @@ def sweep_leg(sindi, corpus, dq, wl, k, tsel, truth, rec_note, steps=3):
             "best_at_recall_0.99": best, "rows": rows}
 
 
-def layout_leg(sindi, corpus, dq, alpha, dtype, gamma, k, ref_ids, ref_scores, steps=3):
+def layout_leg(sindi, corpus, dq, alpha, dtype, gamma, k, ref_ids, ref_scores, beta=1.0,
+               steps=3):
     """Window lambda and score tile T (the GPU's analog of Sec. 3.3.1's window size): tiles of at
     most T documents split each window equally, and one workgroup holds one tile's scores in
     LDS.  Each layout is built on the device and searched over the whole query set; Thm. 3.1
@@ -518,13 +544,13 @@ def layout_leg(sindi, corpus, dq, alpha, dtype, gamma, k, ref_ids, ref_scores, s
         idx = sindi.Index(corpus, alpha=alpha, window=window, value_dtype=dtype, tile=tile,
                           gpu_build=True)
         info = idx.info()
-        idx.search(dq, k, gamma=gamma, out=(ids, sc))
+        idx.search(dq, k, gamma=gamma, beta=beta, out=(ids, sc))
         torch.cuda.synchronize()
         sindi.profile_enable(True)
         sindi.profile_read(reset=True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            idx.search(dq, k, gamma=gamma, out=(ids, sc))
+            idx.search(dq, k, gamma=gamma, beta=beta, out=(ids, sc))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = sindi.profile_read(reset=True)
@@ -558,7 +584,7 @@ def coarse_error(idx, dqs, qs, pruned, k):
 
 
 def precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q, dqs, qs, pruned,
-                  steps=3):
+                  beta=1.0, steps=3):
     """The same search with FP32 and BF16 posting values (each index built on its own):
     throughput, Recall@k and coarse-score error on the same sampled queries."""
     import torch
@@ -568,13 +594,13 @@ def precision_leg(sindi, corpus, dq, wl, alpha, gamma, k, rsel, truth, n_q, dqs,
         idx = sindi.Index(corpus, alpha=alpha, window=wl.window, value_dtype=dt, gpu_build=True)
         ids = torch.empty((n_q, k), dtype=torch.int64, device="cuda")
         sc = torch.empty((n_q, k), dtype=torch.float32, device="cuda")
-        idx.search(dq, k, gamma=gamma, out=(ids, sc))
+        idx.search(dq, k, gamma=gamma, beta=beta, out=(ids, sc))
         torch.cuda.synchronize()
         sindi.profile_enable(True)
         sindi.profile_read(reset=True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            idx.search(dq, k, gamma=gamma, out=(ids, sc))
+            idx.search(dq, k, gamma=gamma, beta=beta, out=(ids, sc))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         pr = sindi.profile_read(reset=True)
