@@ -44,3 +44,20 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_coarse_terms_counted_are_the_beta_mass_prefix():
+    """The algorithmic bytes of a pruned-query run count the beta-mass terms (Sec. 4.1) the
+    scoring pass reads: the same terms the oracle's mass pruning keeps, and every term at
+    beta = 1."""
+    import numpy as np
+    import oracle
+    import synth
+    q = synth.generate(300, 5_000, nnz=("poisson", 30.0), seed=21)
+    assert bench.coarse_queries(q, 1.0) is q
+    rows = np.repeat(np.arange(q.n_rows), np.diff(q.indptr))
+    for beta in (0.3, 0.8, 0.95):
+        c = bench.coarse_queries(q, beta)
+        keep = oracle.mass_prune(q, beta).astype(bool)
+        assert np.array_equal(np.diff(c.indptr), np.bincount(rows[keep], minlength=q.n_rows))
+        assert np.array_equal(c.indices, q.indices[keep])
