@@ -859,11 +859,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 // read-out).  Every wave lays out the tile's chunks itself: the query's terms
 // are taken 64 at a time (a segment, one list per lane), and a wave-wide
 // prefix sum over the lists' chunk counts numbers the segment's chunks.  The
-// waves then take batches of KU consecutive chunks from the segment's counter
-// in LDS (one atomic by the wave's first lane, the next batch taken while the
-// current one's loads are in flight), so they finish the tile together however
-// unevenly the lists' lengths and the adds' bank conflicts fall; the counters
-// are cleared between the tile's two barriers.  The layout needs no LDS table:
+// waves then take batches of KU consecutive chunks: wave w's first batch of a
+// segment is fixed (chunks w KU to w KU + KU - 1, so its loads leave at once),
+// the next ones come from the segment's counter in LDS (one atomic by the
+// wave's first lane, taken while the current batch's loads are in flight), so
+// they finish the tile together however unevenly the lists' lengths and the
+// adds' bank conflicts fall; the counters are reset between the tile's two
+// barriers.  The layout needs no LDS table:
 // a tile costs the two barriers around its read-out.  The first segment's
 // terms, weights and list bounds (the next tile's prefetched during the
 // current one) stay in registers; further segments are reloaded (cache hits).
@@ -942,9 +944,11 @@ __device__ __forceinline__ void accumulate1_item(
     };
     load_run(r_base);
     // The waves take batches of KU chunks of a segment from the segment's counter, so that
-    // they reach the tile's barrier together.
+    // they reach the tile's barrier together; wave w's first batch of a segment is chunks
+    // [w KU, (w + 1) KU), so the counters start past the NW first batches.
+    constexpr uint32_t kFirstTaken = (uint32_t)(NW * KU);
     __shared__ uint32_t s_next[kMaxSeg];
-    for (int i = tid; i < kMaxSeg; i += NT) s_next[i] = 0;
+    for (int i = tid; i < kMaxSeg; i += NT) s_next[i] = kFirstTaken;
     __syncthreads();
 
     for (int64_t ti = ti_beg; ti < ti_end; ++ti) {
@@ -1008,7 +1012,7 @@ __device__ __forceinline__ void accumulate1_item(
                 return uni(g);
             };
             const uint32_t lb = st;
-            uint32_t cs = take();
+            uint32_t cs = (uint32_t)wave * (uint32_t)KU;
             // The list of the wave's last chunk: its chunks end at c_end, its chunk 0 would
             // start at group l_base, it ends at group l_end, its weight is l_w.  A wave's chunk
             // numbers only grow inside a segment, so a chunk below c_end is in that list.
@@ -1071,7 +1075,7 @@ __device__ __forceinline__ void accumulate1_item(
             }
         }
         __syncthreads();
-        if (tid < nseg) s_next[tid] = 0;  // every wave has taken its last batch of the tile
+        if (tid < nseg) s_next[tid] = kFirstTaken;  // every wave has taken its last batch of the tile
 
         // ---- read the row: sample maxima or emit every score at or above the
         // query's threshold (as in k_accumulate)
