@@ -38,7 +38,8 @@ namespace sindi {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kRerankPerWave = 4;  // pool entries one rerank wave scores
+constexpr int kRerankPerWave = 4;  // pool entries one rerank wave scores at a time
+constexpr int kRerankGroups = 4;   // such groups per wave (one query table per workgroup)
 constexpr int kMaxSeg = kQueryHash / 2 / kWave;  // 64-term segments of the longest query
 
 __device__ __forceinline__ uint32_t ord_f32(float f)
@@ -1462,11 +1463,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     if (tid == 0) status[row] = kSlotOk;
 }
 
-// Exact rerank (Alg. 4): each wave scores kRerankPerWave pool entries, one
-// after the other, NW waves per workgroup, grid (slot, entry group); each
-// workgroup builds the query's hash in LDS (2^hlg slots).  The entry's key
-// becomes (FP32 inner product of the unpruned row with the full query, then
-// inverted id).  Slots not finalized are skipped.
+// Exact rerank (Alg. 4): each wave scores kRerankPerWave pool entries at a
+// time, kRerankGroups times, NW waves per workgroup, grid (slot, entry block);
+// each workgroup builds the query's hash in LDS (2^hlg slots) once for its
+// kRerankGroups x NW x kRerankPerWave entries.  The entry's key becomes (FP32
+// inner product of the unpruned row with the full query, then inverted id).
+// Slots not finalized are skipped.
 __global__ __launch_bounds__(kFinThreads) void k_rerank(DevIndex ix, DevQueries q,
                                                         const int32_t *slot_q, int32_t need,
                                                         int32_t hlg, uint64_t *pool,
@@ -1487,57 +1489,66 @@ __global__ __launch_bounds__(kFinThreads) void k_rerank(DevIndex ix, DevQueries 
         return;
     }
     const QueryHash h{hid, hval, nullptr, lg};
-    // This wave's pool entries: their keys and row bounds are loaded before the
-    // query table is built, and the first two 64-entry rounds of every row are
-    // loaded together, so the entries' memory latencies overlap.
     uint64_t *e = pool + (size_t)slot * (size_t)need;
-    const int32_t c0 = ((int32_t)blockIdx.y * NW + wave) * EPW;
     uint32_t lo[EPW];
     int64_t ra[EPW], rb[EPW];
+    // keys and row bounds of the wave's entries [c0, c0 + EPW)
+    auto bounds = [&](int32_t c0) {
 #pragma unroll
-    for (int j = 0; j < EPW; ++j) {
-        lo[j] = 0;
-        ra[j] = rb[j] = 0;
-        if (c0 + j < need) {
-            const uint64_t key = e[c0 + j];
-            lo[j] = (uint32_t)key;
-            const uint32_t doc = key_doc(key);
-            ra[j] = ix.indptr[doc];
-            rb[j] = ix.indptr[doc + 1];
-        }
-    }
-    build_query_hash(q, qa, qb, h);
-    int32_t id[EPW][2];
-    float xv[EPW][2];
-#pragma unroll
-    for (int j = 0; j < EPW; ++j)
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int64_t p = ra[j] + r * kWave + lane;
-            id[j][r] = -1;
-            xv[j][r] = 0.0f;
-            if (p < rb[j]) {
-                id[j][r] = ix.indices[p];
-                xv[j][r] = ix.values[p];
+        for (int j = 0; j < EPW; ++j) {
+            lo[j] = 0;
+            ra[j] = rb[j] = 0;
+            if (c0 + j < need) {
+                const uint64_t key = e[c0 + j];
+                lo[j] = (uint32_t)key;
+                const uint32_t doc = key_doc(key);
+                ra[j] = ix.indptr[doc];
+                rb[j] = ix.indptr[doc + 1];
             }
         }
-    // delta(q, x_doc) in FP32, each lane over entries lane, lane + 64, ... of the
-    // row in order, then summed across the wave
+    };
+    // The first group's keys and row bounds are loaded before the query table is
+    // built, and the first two 64-entry rounds of every row of a group are loaded
+    // together, so the entries' memory latencies overlap.
+    const int32_t first = (int32_t)blockIdx.y * kRerankGroups * NW;
+    bounds((first + wave) * EPW);
+    build_query_hash(q, qa, qb, h);
+    for (int g = 0; g < kRerankGroups; ++g) {
+        const int32_t c0 = (first + g * NW + wave) * EPW;
+        if (c0 >= need) break;  // wave-uniform; no barrier follows
+        if (g > 0) bounds(c0);
+        int32_t id[EPW][2];
+        float xv[EPW][2];
 #pragma unroll
-    for (int j = 0; j < EPW; ++j) {
-        float acc = 0.0f;
+        for (int j = 0; j < EPW; ++j)
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            if (id[j][r] < 0) continue;
-            const int sl = probe(h, id[j][r]);
-            if (sl >= 0) acc = fmaf(h.val[sl], xv[j][r], acc);
+            for (int r = 0; r < 2; ++r) {
+                const int64_t p = ra[j] + r * kWave + lane;
+                id[j][r] = -1;
+                xv[j][r] = 0.0f;
+                if (p < rb[j]) {
+                    id[j][r] = ix.indices[p];
+                    xv[j][r] = ix.values[p];
+                }
+            }
+        // delta(q, x_doc) in FP32, each lane over entries lane, lane + 64, ... of the
+        // row in order, then summed across the wave
+#pragma unroll
+        for (int j = 0; j < EPW; ++j) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (id[j][r] < 0) continue;
+                const int sl = probe(h, id[j][r]);
+                if (sl >= 0) acc = fmaf(h.val[sl], xv[j][r], acc);
+            }
+            for (int64_t p = ra[j] + 2 * kWave + lane; p < rb[j]; p += kWave) {
+                const int sl = probe(h, ix.indices[p]);
+                if (sl >= 0) acc = fmaf(h.val[sl], ix.values[p], acc);
+            }
+            const float sc = wave_sum(acc);
+            if (c0 + j < need && lane == 0) e[c0 + j] = ((uint64_t)ord_f32(sc) << 32) | lo[j];
         }
-        for (int64_t p = ra[j] + 2 * kWave + lane; p < rb[j]; p += kWave) {
-            const int sl = probe(h, ix.indices[p]);
-            if (sl >= 0) acc = fmaf(h.val[sl], ix.values[p], acc);
-        }
-        const float sc = wave_sum(acc);
-        if (c0 + j < need && lane == 0) e[c0 + j] = ((uint64_t)ord_f32(sc) << 32) | lo[j];
     }
 }
 
@@ -1852,7 +1863,7 @@ hipError_t launch_finalize(const DevIndex &ix, const DevQueries &q, const int32_
     const size_t lds_h = ((size_t)1 << hlg) * 8;
     e = set_lds(k_rerank, lds_h);
     if (e != hipSuccess) return e;
-    constexpr int PER_WG = kFinThreads / kWave * kRerankPerWave;
+    constexpr int PER_WG = kFinThreads / kWave * kRerankPerWave * kRerankGroups;
     hipLaunchKernelGGL(k_rerank, dim3((unsigned)n_slots, (unsigned)((need + PER_WG - 1) / PER_WG)),
                        dim3(kFinThreads), lds_h, s, ix, q, slot_q, need, hlg, pool, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
